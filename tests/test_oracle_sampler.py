@@ -1,0 +1,149 @@
+"""Pins of the oracle's Metropolis sampler against the paper's target law.
+
+Eq. 1: the equilibrium density of a cell in (length, solid angle) is
+m^2 exp(-F(m)/kT).  With exchange, DMI and demag off every cell is an
+independent chain (a macrospin), so averages can be checked against 2-D
+quadrature.  In the exact length mode (log-uniform factor, exponent 3) the
+chain samples that law exactly; in the paper's mode (uniform factor,
+exponent 4, Eq. 5) only to leading order in sigma, and the residual bias is
+reported and bounded.  The fitted me, chi of the length histogram recover the
+inputs (the paper's Fig. 2 procedure).
+"""
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+KB = 1.380649e-23
+
+
+def quadrature(S, K1, Bz):
+    c = S.coeffs()
+    V, kT, Ms0 = np.prod(S.cell), KB * S.s.T, S.s.Ms0
+    m = np.linspace(0.0, 1.6, 3201)[1:]
+    ct = np.linspace(-1.0, 1.0, 2001)
+    M, CT = np.meshgrid(m, ct, indexing="ij")
+    q = M * M
+    Fl = c["la"] * (q - c["me"] ** 2) ** 2 if c["below"] else c["lb"] * q + c["lbc"] * q * q
+    F = Fl + V * K1 * (1 - q * CT * CT) / kT - V * Ms0 * Bz * M * CT / kT
+    w = q * np.exp(-(F - F.min()))
+    I = lambda g: np.trapezoid(np.trapezoid(w * g, ct, axis=1), m)
+    Z = I(1.0)
+    return I(M * CT) / Z, I(q) / Z
+
+
+def snapshots(S, m, n, burn, every, cone=30):
+    ser, cone, win = S.run(m, burn, cone_deg=cone, adapt_every=100)
+    out = []
+    sw = burn
+    for _ in range(n):
+        ser, cone, win = S.run(m, every, sweep0=sw, cone_deg=cone, adapt_every=100, window=win)
+        sw += every
+        out.append(m.copy())
+    return np.array(out)      # [n, 3, N]
+
+
+def batch_se(x, nb=10):
+    b = x[: len(x) // nb * nb].reshape(nb, -1).mean(axis=1)
+    return b.mean(), b.std(ddof=1) / np.sqrt(nb)
+
+
+CASES = [(0.43, 5e4), (0.9, 5e5), (0.99, 5e5), (1.01, 5e5), (1.1, 5e5)]
+
+
+@pytest.mark.parametrize("t,K1", CASES)
+def test_macrospin_exact_mode(oracle_mod, t, K1):
+    Tc, Bz = 700.0, 0.1
+    # any sigma is exact in this mode; a wide one mixes the broad length
+    # distribution near and above Tc quickly, Eq. 13's suits the narrow one deep below
+    S = oracle_mod.System((64, 64, 1), (5e-9,) * 3, Ms0=1e6, A0=0.0, K1=K1, Tc=Tc, T=t * Tc, B=(0, 0, Bz),
+                          lenmode=1, sigma_fixed=0.25 if t > 0.8 else 0.0, seed=11)
+    m = S.init_state("uniform")
+    snap = snapshots(S, m, 80, 1500, 10)
+    mz_q, m2_q = quadrature(S, K1, Bz)
+    mz, se_mz = batch_se(snap[:, 2].mean(axis=1))
+    m2, se_m2 = batch_se((snap**2).sum(axis=1).mean(axis=1))
+    assert abs(mz - mz_q) < 4 * se_mz + 1e-4 * abs(mz_q), (mz, mz_q, se_mz)
+    assert abs(m2 - m2_q) < 4 * se_m2 + 1e-4 * m2_q, (m2, m2_q, se_m2)
+
+
+@pytest.mark.parametrize("t", [0.9, 1.1])
+def test_macrospin_paper_mode_bias_is_small(oracle_mod, t):
+    """Paper's rule with Eq. 13's sigma: the stationary law matches Eq. 1 to
+    leading order in sigma; the bias in <m^2> stays below 2 %."""
+    Tc, Bz, K1 = 700.0, 0.1, 5e5
+    S = oracle_mod.System((64, 64, 1), (5e-9,) * 3, Ms0=1e6, A0=0.0, K1=K1, Tc=Tc, T=t * Tc, B=(0, 0, Bz),
+                          lenmode=0, seed=12)
+    m = S.init_state("uniform")
+    burn = 3000 if t > 1 else 400
+    snap = snapshots(S, m, 50, burn, 40 if t > 1 else 10)
+    _, m2_q = quadrature(S, K1, Bz)
+    m2, se = batch_se((snap**2).sum(axis=1).mean(axis=1))
+    assert abs(m2 / m2_q - 1) < 0.02 + 4 * se / m2_q
+
+
+def test_length_fit_recovers_me_chi(oracle_mod):
+    """Fit Eq. 7 to the sampled length distribution (K = H = 0): recovers me, chi."""
+    Tc, T = 700.0, 600.0
+    S = oracle_mod.System((64, 64, 1), (3e-9,) * 3, Ms0=1e6, A0=0.0, K1=0.0, Tc=Tc, T=T,
+                          lenmode=1, sigma_fixed=0.25, seed=13)
+    c = S.coeffs()
+    m = S.init_state("uniform")
+    snap = snapshots(S, m, 40, 300, 10)
+    L = np.sqrt((snap**2).sum(axis=1)).ravel()
+    grid = np.linspace(1e-4, 1.6, 8001)
+
+    def nll(p):
+        me2, la = p[0], np.exp(p[1])
+        logw = lambda x: 2 * np.log(x) - la * (x * x - me2) ** 2
+        lg = logw(grid)
+        Z = np.log(np.trapezoid(np.exp(lg - lg.max()), grid)) + lg.max()
+        return -(logw(L).sum() - len(L) * Z) / len(L)
+
+    r = minimize(nll, [c["me"] ** 2 * 1.1, np.log(c["la"]) - 0.2], method="Nelder-Mead",
+                 options={"xatol": 1e-9, "fatol": 1e-12, "maxiter": 4000})
+    me_fit, la_fit = np.sqrt(r.x[0]), np.exp(r.x[1])
+    assert abs(me_fit / c["me"] - 1) < 2e-3
+    # la = V Ms0 / (8 chi me^2 kT) -> chi recovered through la
+    assert abs(la_fit / c["la"] - 1) < 0.03
+
+
+def test_checkerboard_colours(oracle_mod):
+    S = oracle_mod.System((7, 6, 3), (5e-9,) * 3, Ms0=1e6, A0=1e-11, K1=5e5, Tc=700.0, T=300.0)
+    m = S.init_state("random")
+    seen = np.zeros(S.N, dtype=int)
+    nx, ny, nz = S.grid
+    for colour in (0, 1):
+        m1, acc, _, _, _ = S.subsweep(m, 0, colour, 30.0)
+        mine = acc >= 0
+        seen += mine
+        changed = np.any(m1 != m, axis=0)
+        assert not np.any(changed & ~mine)              # only own-colour cells move
+        idx = np.arange(S.N)
+        x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+        assert np.all(((x + y + z) % 2 == colour) == mine)
+    assert np.all(seen == 1)                            # one trial per cell per sweep
+
+
+def test_cone_adaptation_rule(oracle_mod):
+    # no coupling, tiny moves at high T -> acceptance ~1 -> +1 degree per window
+    S = oracle_mod.System((8, 8, 1), (5e-9,) * 3, Ms0=1e6, A0=0.0, K1=0.0, Tc=700.0, T=1400.0,
+                          sigma_fixed=1e-4)
+    m = S.init_state("uniform")
+    _, cone, win = S.run(m, 500, cone_deg=30, adapt_every=100)
+    assert cone == 35 and win == 0
+    # strong exchange at low T, huge cone -> acceptance << 0.45 -> -1 degree per window
+    S = oracle_mod.System((8, 8, 1), (5e-9,) * 3, Ms0=1e6, A0=1e-11, K1=5e5, Tc=700.0, T=50.0, sigma_fixed=1e-3)
+    m = S.init_state("uniform")
+    _, cone, win = S.run(m, 300, cone_deg=120, adapt_every=100)
+    assert cone == 117
+    _, cone, win = S.run(m, 250, sweep0=300, cone_deg=120, adapt_every=100)
+    assert cone == 118                                  # sweeps 399 and 499 close a window
+
+
+def test_deterministic(oracle_mod):
+    S = oracle_mod.System((9, 7, 2), (5e-9,) * 3, Ms0=1e6, A0=1e-11, K1=5e5, Tc=700.0, T=500.0, demag=True)
+    a = S.init_state("random")
+    b = a.copy()
+    S.run(a, 20, cone_deg=30, adapt_every=5)
+    S.run(b, 20, cone_deg=30, adapt_every=5)
+    assert np.array_equal(a, b)
