@@ -1,0 +1,145 @@
+#!/usr/bin/env python3
+"""Throughput of the micromagnetic Monte Carlo hot path on one MI355X.
+
+A step is one full MMC sweep (paper Sec. II: one compound trial move per cell,
+red then black colour pass), each colour pass preceded by a demag refresh
+(FFT convolution with the cell-averaged tensor, Sec. III, Eq. 14), on the
+1024x1024x4 grid of 5 nm cells at T = 0.9 Tc with 1 T applied along z.
+Prints one JSON line: cell-updates/s, the roofline figure of the dominant
+kernel (algorithmic bytes / HIP-event-timed launch duration) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+KINDS = ["demag_xfwd", "demag_ypass", "demag_xinv", "colour_pass", "end_of_sweep"]
+
+
+def pad_pow2(n, minimum=1):
+    p = 1
+    while p < 2 * n - 1:
+        p *= 2
+    return max(p, minimum)
+
+
+def algorithmic_bytes(grid, demag, kind):
+    """Minimum HBM bytes one launch of `kind` must move (FP32 data)."""
+    nx, ny, nz = grid
+    N = nx * ny * nz
+    Px, Py = pad_pow2(nx, 2), pad_pow2(ny)
+    L, S = Px // 2, 3 * nz
+    spec = (L + 1) * S * ny * 8                     # x-spectrum, complex FP32
+    tensor = (L + 1) * (Py // 2 + 1) * 6 * nz * 4   # tensor spectrum, FP32
+    if kind == "demag_xfwd":
+        return 12 * N + spec                        # read m, write spectrum
+    if kind == "demag_ypass":
+        return 2 * spec + tensor                    # read + write spectrum, read tensor
+    if kind == "demag_xinv":
+        return spec + 12 * N // 2                   # read spectrum, write h of one colour
+    if kind == "colour_pass":
+        per = 12 + 12 + 12 + (12 if demag else 0)   # own m, other m, own write, own h
+        return per * N // 2
+    return 0
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle (as it stands) on a 256x256x4 section of the same workload."""
+    from oracle import oracle as O
+    wl = workloads.WORKLOADS["loop_1024x1024x4"]
+    mat = workloads.BASE_MATERIAL
+    grid = (256, 256, 4)
+    S = O.System(grid, wl["cell"], Ms0=mat["Ms0"], A0=mat["A0"], K1=mat["K1"], Tc=mat["Tc"], T=wl["T"],
+                 B=wl["B"], demag=True, mf=mat["mf"])
+    m = S.init_state("uniform")
+    _ = S.plan                                       # tensor setup, not timed (as on the GPU side)
+    S.run(m, 1, cone_deg=30, adapt_every=100)        # warm-up sweep
+    n, t = 0, 0.0
+    while t < seconds_target and n < 200:
+        t0 = time.perf_counter()
+        S.run(m, 2, sweep0=1 + n, cone_deg=30, adapt_every=100)
+        t += time.perf_counter() - t0
+        n += 2
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cells = int(np.prod(grid))
+    return {"value": cells * n / t, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d sweeps of a 256x256x4 section (same cell, material, T, field, demag on), %.1f s" % (n, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2106_05593_amd import Chain
+
+    torch.cuda.set_device(0)
+    wl = workloads.WORKLOADS["loop_1024x1024x4"]
+    mat = workloads.BASE_MATERIAL
+    grid = wl["grid"]
+    N = int(np.prod(grid))
+    print("bench: creating %s chain (demag on)" % (grid,), file=sys.stderr, flush=True)
+    ch = Chain(grid, wl["cell"], Ms0=mat["Ms0"], A0=mat["A0"], K1=mat["K1"], Tc=mat["Tc"], T=wl["T"], B=wl["B"],
+               mf=mat["mf"], mu=mat["mu"], demag=True, adapt_every=wl["adapt_every"], cone_deg=wl["cone_deg"],
+               seed=0, init=0)
+    ch.sweep(args.warmup)
+    ch.sync()
+    torch.cuda.synchronize()
+    print("bench: warm-up done, timing %d sweeps" % args.steps, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ms, cnt = ch.sweep_timed(args.steps)             # synchronises the stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ch.stats()
+    assert st["sweeps"] == args.warmup + args.steps and np.isfinite(st["m2_mean"])
+    value = N * args.steps / wall
+
+    per_kernel = {}
+    for k, name in enumerate(KINDS):
+        if cnt[k] == 0:
+            continue
+        avg_us = 1e3 * ms[k] / cnt[k]
+        b = algorithmic_bytes(grid, True, name)
+        per_kernel[name] = {"launches": int(cnt[k]), "avg_us": round(avg_us, 3), "total_ms": round(float(ms[k]), 3),
+                            "alg_bytes": b, "GBs": round(b / (avg_us * 1e-6) / 1e9, 1) if b else None}
+    dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
+    ach = per_kernel[dom]["GBs"]
+    roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
+    sweep_bytes = sum(algorithmic_bytes(grid, True, n) * cnt[k] for k, n in enumerate(KINDS)) / args.steps
+    out = {
+        "metric": "MC cell-updates/s at 1024x1024x4 w/ demag; batched chains/s vs plain, FP32",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "loop_1024x1024x4", "grid": list(grid), "cell_nm": 5, "T_K": wl["T"],
+                   "mu0H_T": wl["B"][2], "demag_refresh_per_sweep": 2, "sweep_alg_bytes_per_cell": round(sweep_bytes / N, 1)},
+        "roofline": roofline,
+        "kernels": per_kernel,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

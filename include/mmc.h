@@ -1,0 +1,207 @@
+/*
+ * mmc.h -- C-ABI of libmmc, an MI355X (gfx950) implementation of the
+ * micromagnetic Monte Carlo (MMC) method with variable magnetization length
+ * (S. Lepadatu, arXiv 2106.05593).
+ *
+ * What the library computes (paper references are to that article):
+ *   - Equilibrium states of a discretised ferromagnet sampled by a Markov
+ *     chain whose stationary law is the Maxwell-Boltzmann-type density
+ *     m^2 exp(-F(m)/kT) of Sec. II, Eq. 1.
+ *   - One sweep ("MMC iteration", Sec. II, steps 1-4) gives every cell one
+ *     compound trial move: a rotation uniform in a cone about the current
+ *     direction, then a multiplicative length change, accepted with
+ *     min{1, (mB/mA)^k exp(-dF/kT)} (Eq. 5, k = 4; see mmc_lenmove).
+ *     Cells are updated in two colour passes of a red-black checkerboard
+ *     (colour = (x+y+z) mod 2, colour 0 first), which makes every pass fully
+ *     parallel.
+ *   - dF sums exchange (Eq. 10, as the exact change of the bond energy
+ *     sum_bonds V A0 |m_i - m_j|^2 / h^2), interfacial DMI (Eq. 15), uniaxial
+ *     anisotropy (Eq. 11), Zeeman, the longitudinal LLB term (exponent of
+ *     Eq. 7, parameterised by me(T), Eq. 9 and chi_par(T), Eq. 8) and the
+ *     demag term with a frozen field (Sec. III, Eq. 14): H_d = -N*M by
+ *     zero-padded FFT convolution with the cell-averaged (Newell) tensor,
+ *     refreshed before each colour pass (or once per sweep) and constant
+ *     within a pass.
+ *   - The cone half-angle is adapted every adapt_every sweeps by +-1 degree to
+ *     keep the acceptance rate within 0.5 +- 0.05 (Sec. II).  The length
+ *     move width sigma follows Eq. 13, capped at 0.03, and 0.03 at T >= Tc.
+ *
+ * Conventions
+ *   - Units are SI.  Fields are given as mu0*H in tesla.  m = M/Ms0 is
+ *     dimensionless and not unit length.  Demag fields h returned by the
+ *     library are H_d/Ms0 (dimensionless).
+ *   - Grids are nx*ny*nz cells, open boundaries.  "Natural SoA" arrays hold
+ *     3*N floats: component c of cell (x,y,z) at c*N + x + nx*(y + ny*z).
+ *   - Randomness is Philox4x32-10 (Salmon et al., SC'11) with key = seed and
+ *     counter = (cell index, sweep mod 2^32, chain_id, 2*tag + colour);
+ *     tag 0: trial moves, tag 1: random initial directions.  Each uniform is
+ *     (x >> 8) * 2^-24.
+ *   - The library owns every context and its device memory; the caller owns
+ *     every pointer it passes in and keeps it valid for the call only.
+ *   - on_device = 1 means the pointer is device memory on the context's GPU
+ *     (e.g. a PyTorch tensor's data_ptr()); 0 means host memory.
+ *   - Calls that enqueue work (mmc_sweep, mmc_batch_sweep) are asynchronous
+ *     on the context's stream; getters synchronise that stream.
+ *   - A context is not thread-safe; distinct contexts are.
+ *   - Every call returns an mmc_status; no exception or abort crosses the ABI.
+ *     On failure mmc_last_error() gives a thread-local message.  A device
+ *     error (kernel fault, out of memory on the device) is returned as
+ *     MMC_ERR_DEVICE and leaves the context unusable except for destroy.
+ */
+#ifndef MMC_H
+#define MMC_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MMC_OK = 0,
+    MMC_ERR_ARG = -1,          /* invalid argument (NULL, size, enum, negative count) */
+    MMC_ERR_DOMAIN = -2,       /* physically invalid value (T <= 0, Ms0 <= 0, ...) */
+    MMC_ERR_OOM = -3,          /* host or device allocation failed */
+    MMC_ERR_DEVICE = -4,       /* HIP runtime or kernel error */
+    MMC_ERR_STATE = -5,        /* call not valid in the current state */
+    MMC_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
+} mmc_status;
+
+typedef struct { int32_t nx, ny, nz; } mmc_grid;          /* each >= 1, nx,ny <= 4096, nz <= 8 with demag */
+typedef struct { double hx, hy, hz; } mmc_cellsize;       /* metres, > 0 */
+
+/* Mean-field model behind me(T) and chi_par(T). */
+typedef enum {
+    MMC_MF_LANGEVIN = 0,        /* Eqs. 8-9 as printed (classical spins) */
+    MMC_MF_BRILLOUIN_HALF = 1   /* J = 1/2: me = tanh(me Tc/T) */
+} mmc_mf;
+
+/* Length trial move and the acceptance exponent k of (mB/mA)^k. */
+typedef enum {
+    MMC_LEN_PAPER = 0,   /* factor uniform in [1-sigma, 1+sigma], k = 4 (Sec. II, Eq. 5) */
+    MMC_LEN_EXACT = 1    /* ln(factor) uniform in [-ln(1+sigma), ln(1+sigma)], k = 3:
+                            the exact Metropolis-Hastings ratio for the Eq. 1 target */
+} mmc_lenmove;
+
+typedef enum {
+    MMC_DEMAG_OFF = 0,
+    MMC_DEMAG_FP32 = 1          /* FFT convolution in FP32, tensor spectrum from FP64 */
+} mmc_demag;
+
+typedef struct {
+    double Ms0;          /* zero-temperature saturation magnetization, A/m, > 0 */
+    double A0;           /* exchange stiffness at T = 0 (A = A0 me^2), J/m, >= 0 */
+    double D0;           /* interfacial DMI constant at T = 0 (D = D0 me^2), J/m^2 */
+    double K1, K2;       /* uniaxial anisotropy constants, J/m^3 */
+    double easy_axis[3]; /* need not be normalised, non-zero */
+    double Tc;           /* Curie temperature, K, > 0 */
+    double mu_atomic;    /* atomic moment, J/T, > 0 (Bohr magneton for J = 1/2, g = 2) */
+    int32_t mf;          /* mmc_mf */
+} mmc_material;
+
+typedef struct {
+    uint64_t seed;
+    uint32_t chain_id;
+    int32_t cone_deg;           /* initial cone half-angle, integer degrees in [1, 180] */
+    int32_t adapt_every;        /* sweeps per cone adaptation; 0 disables (paper: 100) */
+    double sigma_fixed;         /* > 0: fixed length-move width; <= 0: Eq. 13 capped at 0.03 */
+    int32_t lenmove;            /* mmc_lenmove */
+    int32_t demag;              /* mmc_demag */
+    int32_t refresh_per_sweep;  /* 2: refresh H_d before each colour pass; 1: once per sweep */
+    double T;                   /* temperature, K, > 0 */
+    double B[3];                /* applied field mu0*H, tesla */
+    int32_t init;               /* initial state: 0 uniform along init_dir, 1 random directions (tag 1);
+                                   length me(T) below Tc, sqrt(<m^2>) of Eq. 7 at and above Tc */
+    double init_dir[3];
+} mmc_run;
+
+typedef struct mmc_ctx mmc_ctx;
+typedef struct mmc_batch mmc_batch;
+
+/* Create a chain: validates arguments, solves the mean field (FP64, host),
+ * builds the demag tensor spectrum (FP64, host), allocates device state and
+ * writes the initial state.  hip_stream: a hipStream_t to enqueue on, or NULL
+ * for a library-owned stream.  *out is set only on MMC_OK. */
+mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_material* mat,
+                      const mmc_run* run, void* hip_stream, mmc_ctx** out);
+void mmc_destroy(mmc_ctx* ctx);
+
+/* Granular material (Sec. III, granular film): per-cell grain id (host, N values
+ * < n_grains), per-grain easy axis, K1, K2 and Tc; exchange across grain
+ * boundaries is scaled by boundary_exchange_scale.  Re-derives the per-grain
+ * me, chi_par and sigma and re-initialises the state as mmc_run.init asks. */
+mmc_status mmc_set_grains(mmc_ctx* ctx, const uint32_t* grain_of_cell, uint32_t n_grains,
+                          const double* easy_axis3, const double* K1, const double* K2,
+                          const double* Tc, double boundary_exchange_scale);
+
+mmc_status mmc_set_field(mmc_ctx* ctx, const double mu0H_tesla[3]);
+/* Re-solves me(T), chi_par(T), sigma; the state is kept. */
+mmc_status mmc_set_temperature(mmc_ctx* ctx, double T_kelvin);
+
+/* State in/out, natural SoA layout (3*N floats).  set: every |m_i| > 0 and
+ * finite, else MMC_ERR_DOMAIN.  get synchronises the stream. */
+mmc_status mmc_set_m(mmc_ctx* ctx, const float* m, int on_device);
+mmc_status mmc_get_m(mmc_ctx* ctx, float* out, int on_device);
+
+/* Enqueue n full sweeps (n >= 0). */
+mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n);
+/* As mmc_sweep, and copies per-sweep statistics to host `series` (n*5 doubles:
+ * <mx>, <my>, <mz>, <|m|^2> (FP64 reductions) and the accepted-move count). */
+mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series);
+
+/* Instrumented sweeps: as mmc_sweep, with HIP events recorded on the
+ * context's stream before and after every kernel launch; synchronises and
+ * returns the summed device time (ms) and the launch count per kernel kind:
+ * 0 demag x-forward FFT, 1 demag y-pass (FFT, layer mixing, inverse FFT),
+ * 2 demag x-inverse FFT, 3 colour pass, 4 end-of-sweep reduction. */
+mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, double ms_out[5], int32_t launches_out[5]);
+
+/* Total free energy (J) and its split {exchange, DMI, anisotropy, Zeeman,
+ * longitudinal, demag}, with a freshly computed demag field, FP64 sums. */
+mmc_status mmc_energy(mmc_ctx* ctx, double* E_total_J, double E_terms_J[6]);
+
+/* Demag field h = H_d/Ms0 of the current state, natural SoA (3*N floats). */
+mmc_status mmc_demag_field(mmc_ctx* ctx, float* h_out, int on_device);
+
+/* One colour pass (Sec. II steps 1-4 for the cells of one colour) with the
+ * given frozen field h (natural SoA, H_d/Ms0, device or NULL for none) at the
+ * current sweep counter and cone angle; writes per-cell decisions (device,
+ * N bytes: 1 accepted, 0 rejected, 255 other colour).  Counters and the
+ * cone are left unchanged.  For checking the sweep against a reference. */
+mmc_status mmc_subsweep(mmc_ctx* ctx, int32_t colour, const float* h_in_device, uint8_t* acc_out_device);
+
+typedef struct {
+    uint64_t sweeps;          /* sweeps done (the sweep counter) */
+    uint64_t accepts_window;  /* accepted moves since the last cone adaptation */
+    int32_t cone_deg;
+    double sigma;             /* class 0 length-move width */
+    double me;                /* class 0 equilibrium length */
+    double m_mean[3];         /* <m> after the last sweep */
+    double m2_mean;           /* <|m|^2> after the last sweep */
+    uint64_t accepts_last;    /* accepted moves in the last sweep */
+} mmc_stats;
+mmc_status mmc_get_stats(mmc_ctx* ctx, mmc_stats* out);
+
+/* Run state for checkpoint/resume: with the state m this restores a chain
+ * bit-exactly (the generator is stateless). */
+mmc_status mmc_get_state(mmc_ctx* ctx, uint64_t* sweep, int32_t* cone_deg, uint64_t* accepts_window);
+mmc_status mmc_set_state(mmc_ctx* ctx, uint64_t sweep, int32_t cone_deg, uint64_t accepts_window);
+
+/* Batches: independent chains (any sizes, temperatures, fields) advanced
+ * together.  mmc_batch_sweep enqueues n sweeps of every chain as one HIP graph
+ * launch on the first chain's stream; chains stay caller-owned, must outlive
+ * the batch and must not be used directly while a batch sweep runs.  All
+ * chains must be on the same device.  Results equal running each chain alone. */
+mmc_status mmc_batch_create(mmc_ctx* const* chains, int32_t n, mmc_batch** out);
+mmc_status mmc_batch_sweep(mmc_batch* batch, int32_t n);
+mmc_status mmc_batch_sync(mmc_batch* batch);
+void mmc_batch_destroy(mmc_batch* batch);
+
+/* Synchronise the context's stream. */
+mmc_status mmc_sync(mmc_ctx* ctx);
+
+const char* mmc_status_str(mmc_status s);
+const char* mmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,703 @@
+// C-ABI of libmmc (include/mmc.h): contexts, device buffers and the order of
+// kernel launches of a sweep.  All physics setup is FP64 on the host.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mmc_internal.h"
+
+using namespace mmc;
+
+namespace {
+thread_local std::string g_err;
+
+mmc_status fail(mmc_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCK(expr)                                                                                  \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) {                                                                      \
+            if (ctx) ctx->dead = true;                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? MMC_ERR_OOM : MMC_ERR_DEVICE, "%s: %s (%s:%d)", #expr, \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                                  \
+        }                                                                                            \
+    } while (0)
+
+int pad_pow2(int n, int minimum) {
+    int p = 1;
+    while (p < 2 * n - 1) p <<= 1;
+    return std::max(p, minimum);
+}
+int ilog2i(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
+}  // namespace
+
+struct mmc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool dead = false;
+    mmc_grid g{};
+    mmc_cellsize cs{};
+    mmc_material mat{};
+    mmc_run run{};
+    long long N = 0, Nc = 0;
+    int hw = 0;
+    double V = 0;
+    // material classes (grains)
+    int nclass = 1;
+    bool has_classes = false;
+    std::vector<double> ea, K1, K2, Tc;
+    double bscale = 1.0;
+    std::vector<ClassCoef> ctab;
+    ClassCoef* d_ctab = nullptr;
+    uint32_t* d_cid = nullptr;
+    // state
+    float* d_m = nullptr;        // [2][3][Nc] colour-split
+    float* d_h = nullptr;        // [2][3][Nc] colour-split demag field
+    float* d_nat = nullptr;      // 3N natural staging
+    DevState* d_st = nullptr;
+    double* d_part = nullptr;    // [2][nblk][4]
+    unsigned long long* d_pacc = nullptr;
+    int nblk = 0;
+    double* d_epart = nullptr;
+    int epart_n = 0;
+    double* d_series = nullptr;
+    int series_cap = 0;
+    // demag
+    bool demag = false;
+    DemagPlan plan{};
+    float2* d_tw = nullptr;
+    SweepArgs args{};
+    unsigned long long host_sweep = 0;
+    unsigned version = 0;        // bumps when kernel arguments change
+};
+
+struct mmc_batch {
+    std::vector<mmc_ctx*> ch;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> done;
+    hipEvent_t fork = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_n = -1;
+    std::vector<unsigned> versions;
+};
+
+static void update_args(mmc_ctx* c) {
+    SweepArgs& a = c->args;
+    const double kT = kB * c->run.T;
+    a.nx = c->g.nx; a.ny = c->g.ny; a.nz = c->g.nz; a.hw = c->hw; a.Nc = c->Nc;
+    a.wx = (float)(c->V * c->mat.A0 / (c->cs.hx * c->cs.hx * kT));
+    a.wy = (float)(c->V * c->mat.A0 / (c->cs.hy * c->cs.hy * kT));
+    a.wz = (float)(c->V * c->mat.A0 / (c->cs.hz * c->cs.hz * kT));
+    a.cdx = (float)(c->V * c->mat.D0 / (c->cs.hx * kT));
+    a.cdy = (float)(c->V * c->mat.D0 / (c->cs.hy * kT));
+    a.bx = (float)(c->V * c->mat.Ms0 * c->run.B[0] / kT);
+    a.by = (float)(c->V * c->mat.Ms0 * c->run.B[1] / kT);
+    a.bz = (float)(c->V * c->mat.Ms0 * c->run.B[2] / kT);
+    a.cdm = (float)(kMu0 * c->V * c->mat.Ms0 * c->mat.Ms0 / kT);
+    a.bscale = (float)c->bscale;
+    a.k0 = (uint32_t)(c->run.seed & 0xFFFFFFFFull);
+    a.k1 = (uint32_t)(c->run.seed >> 32);
+    a.chain = c->run.chain_id;
+    c->version++;
+}
+
+static mmc_status upload_classes(mmc_ctx* ctx) {
+    ctx->ctab.resize(ctx->nclass);
+    for (int k = 0; k < ctx->nclass; ++k)
+        ctx->ctab[k] = class_coef(ctx->mat, ctx->run.T, ctx->V, ctx->K1[k], ctx->K2[k], &ctx->ea[3 * k], ctx->Tc[k],
+                                  ctx->run.sigma_fixed, 1);
+    if (ctx->d_ctab) { HIPCK(hipFree(ctx->d_ctab)); ctx->d_ctab = nullptr; }
+    HIPCK(hipMalloc(&ctx->d_ctab, sizeof(ClassCoef) * ctx->nclass));
+    HIPCK(hipMemcpyAsync(ctx->d_ctab, ctx->ctab.data(), sizeof(ClassCoef) * ctx->nclass, hipMemcpyHostToDevice,
+                         ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MMC_OK;
+}
+
+static mmc_status init_state(mmc_ctx* ctx) {
+    const double* d = ctx->run.init_dir;
+    double n = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double u[3] = {0, 0, 1};
+    if (n > 0) { u[0] = d[0] / n; u[1] = d[1] / n; u[2] = d[2] / n; }
+    HIPCK(launch_init(ctx->args, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->run.init, (float)u[0], (float)u[1],
+                      (float)u[2], ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MMC_OK;
+}
+
+// Launch sequence of n sweeps.  With `prof`, HIP events bracket every launch
+// (kinds: 0 demag x-forward, 1 demag y-pass, 2 demag x-inverse, 3 colour pass,
+// 4 end of sweep).
+struct LaunchProf {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    size_t used = 0;
+};
+
+static mmc_status enqueue_sweeps(mmc_ctx* ctx, int n, double* series, unsigned long long rec_base,
+                                 LaunchProf* prof = nullptr) {
+    auto mark = [&](int kind) -> hipError_t {
+        if (!prof) return hipSuccess;
+        if (prof->used + 1 >= prof->ev.size()) return hipErrorInvalidValue;
+        if (kind >= 0) prof->kind.push_back(kind);
+        return hipEventRecord(prof->ev[prof->used++], ctx->stream);
+    };
+    for (int s = 0; s < n; ++s) {
+        for (int c = 0; c < 2; ++c) {
+            const bool refresh = ctx->demag && (c == 0 || ctx->run.refresh_per_sweep >= 2);
+            if (refresh) {
+                const int mask = ctx->run.refresh_per_sweep >= 2 ? (1 << c) : 3;
+                for (int stage = 0; stage < 3; ++stage) {
+                    HIPCK(mark(-1));
+                    HIPCK(launch_demag_stage(stage, ctx->args, ctx->plan, ctx->d_m, ctx->d_h, mask, ctx->d_tw, ctx->stream));
+                    HIPCK(mark(stage));
+                }
+            }
+            HIPCK(mark(-1));
+            HIPCK(launch_subsweep(ctx->args, ctx->has_classes, ctx->demag, ctx->run.lenmove == MMC_LEN_EXACT,
+                                  ctx->mat.D0 != 0.0, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, c, ctx->d_st,
+                                  ctx->d_part + (size_t)c * 4 * ctx->nblk, ctx->d_pacc + (size_t)c * ctx->nblk,
+                                  nullptr, ctx->stream, nullptr));
+            HIPCK(mark(3));
+        }
+        HIPCK(mark(-1));
+        HIPCK(launch_finalize(ctx->d_part, ctx->d_pacc, ctx->nblk, ctx->N, ctx->d_st, series, rec_base, ctx->stream));
+        HIPCK(mark(4));
+    }
+    ctx->host_sweep += (unsigned long long)n;
+    return MMC_OK;
+}
+
+static mmc_status check_live(mmc_ctx* ctx) {
+    if (!ctx) return fail(MMC_ERR_ARG, "NULL context");
+    if (ctx->dead) return fail(MMC_ERR_STATE, "context had a device error; destroy it");
+    HIPCK(hipSetDevice(ctx->device));
+    return MMC_OK;
+}
+
+extern "C" {
+
+const char* mmc_status_str(mmc_status s) {
+    switch (s) {
+        case MMC_OK: return "ok";
+        case MMC_ERR_ARG: return "invalid argument";
+        case MMC_ERR_DOMAIN: return "value outside the physical domain";
+        case MMC_ERR_OOM: return "out of memory";
+        case MMC_ERR_DEVICE: return "device error";
+        case MMC_ERR_STATE: return "invalid state";
+        case MMC_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* mmc_last_error(void) { return g_err.c_str(); }
+
+void mmc_destroy(mmc_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    void* bufs[] = {ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, ctx->d_nat, ctx->d_st, ctx->d_part, ctx->d_pacc,
+                    ctx->d_epart, ctx->d_series, ctx->plan.X, ctx->plan.K, ctx->d_tw};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_material* mat, const mmc_run* run,
+                      void* hip_stream, mmc_ctx** out) {
+    mmc_ctx* ctx = nullptr;
+    if (!grid || !cell || !mat || !run || !out) return fail(MMC_ERR_ARG, "NULL argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || grid->nx > 4096 || grid->ny > 2048 || grid->nz > 4096)
+        return fail(MMC_ERR_ARG, "grid %d x %d x %d out of range", grid->nx, grid->ny, grid->nz);
+    if (!(cell->hx > 0 && cell->hy > 0 && cell->hz > 0) || !std::isfinite(cell->hx * cell->hy * cell->hz))
+        return fail(MMC_ERR_DOMAIN, "cell sizes must be positive");
+    if (!(mat->Ms0 > 0) || !(mat->A0 >= 0) || !(mat->Tc > 0) || !(mat->mu_atomic > 0) || !std::isfinite(mat->D0) ||
+        !std::isfinite(mat->K1) || !std::isfinite(mat->K2))
+        return fail(MMC_ERR_DOMAIN, "invalid material constants");
+    if (mat->mf != MMC_MF_LANGEVIN && mat->mf != MMC_MF_BRILLOUIN_HALF) return fail(MMC_ERR_ARG, "unknown mean-field model");
+    const double ean = std::sqrt(mat->easy_axis[0] * mat->easy_axis[0] + mat->easy_axis[1] * mat->easy_axis[1] +
+                                 mat->easy_axis[2] * mat->easy_axis[2]);
+    if (!(ean > 0) || !std::isfinite(ean)) return fail(MMC_ERR_DOMAIN, "easy axis must be non-zero");
+    if (!(run->T > 0) || !std::isfinite(run->T)) return fail(MMC_ERR_DOMAIN, "temperature must be > 0");
+    if (run->cone_deg < 1 || run->cone_deg > 180) return fail(MMC_ERR_ARG, "cone_deg must be in [1, 180]");
+    if (run->adapt_every < 0) return fail(MMC_ERR_ARG, "adapt_every must be >= 0");
+    if (run->lenmove != MMC_LEN_PAPER && run->lenmove != MMC_LEN_EXACT) return fail(MMC_ERR_ARG, "unknown lenmove");
+    if (run->demag != MMC_DEMAG_OFF && run->demag != MMC_DEMAG_FP32) return fail(MMC_ERR_ARG, "unknown demag mode");
+    if (run->refresh_per_sweep != 1 && run->refresh_per_sweep != 2) return fail(MMC_ERR_ARG, "refresh_per_sweep must be 1 or 2");
+    if (run->init != 0 && run->init != 1) return fail(MMC_ERR_ARG, "init must be 0 or 1");
+    if (!(run->sigma_fixed < 1.0)) return fail(MMC_ERR_DOMAIN, "sigma_fixed must be < 1");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(run->B[k])) return fail(MMC_ERR_DOMAIN, "field must be finite");
+    if (run->demag) {
+        if (grid->nz > 8) return fail(MMC_ERR_UNSUPPORTED, "demag needs nz <= 8");
+        const int Py = pad_pow2(grid->ny, 1);
+        const int bins = Py <= 256 ? 1 : Py / 256;
+        if (3 * grid->nz * bins > 96) return fail(MMC_ERR_UNSUPPORTED, "demag: 3*nz*max(1,Py/256) must be <= 96");
+    }
+
+    ctx = new (std::nothrow) mmc_ctx();
+    if (!ctx) return fail(MMC_ERR_OOM, "host allocation failed");
+    mmc_status st = MMC_OK;
+    do {
+        ctx->g = *grid; ctx->cs = *cell; ctx->mat = *mat; ctx->run = *run;
+        if (hipGetDevice(&ctx->device) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "no HIP device"); break; }
+        if (hip_stream) ctx->stream = (hipStream_t)hip_stream;
+        else {
+            if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+                st = fail(MMC_ERR_DEVICE, "stream creation failed");
+                break;
+            }
+            ctx->own_stream = true;
+        }
+        ctx->N = (long long)grid->nx * grid->ny * grid->nz;
+        ctx->hw = (grid->nx + 1) / 2;
+        ctx->Nc = (long long)grid->nz * grid->ny * ctx->hw;
+        ctx->V = cell->hx * cell->hy * cell->hz;
+        ctx->nclass = 1;
+        ctx->ea.assign(mat->easy_axis, mat->easy_axis + 3);
+        ctx->K1.assign(1, mat->K1); ctx->K2.assign(1, mat->K2); ctx->Tc.assign(1, mat->Tc);
+        ctx->demag = run->demag != MMC_DEMAG_OFF;
+        update_args(ctx);
+        st = upload_classes(ctx);
+        if (st != MMC_OK) break;
+        const size_t msz = sizeof(float) * 6 * (size_t)ctx->Nc;
+        auto alloc = [&](void** p, size_t bytes) -> bool {
+            hipError_t e = hipMalloc(p, bytes);
+            if (e != hipSuccess) {
+                st = fail(e == hipErrorOutOfMemory ? MMC_ERR_OOM : MMC_ERR_DEVICE, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+                return false;
+            }
+            return true;
+        };
+        if (!alloc((void**)&ctx->d_m, msz)) break;
+        if (hipMemset(ctx->d_m, 0, msz) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "memset"); break; }
+        if (!alloc((void**)&ctx->d_h, msz)) break;
+        if (hipMemset(ctx->d_h, 0, msz) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "memset"); break; }
+        if (!alloc((void**)&ctx->d_st, sizeof(DevState))) break;
+        ctx->nblk = subsweep_blocks(ctx->args);
+        if (!alloc((void**)&ctx->d_part, sizeof(double) * 8 * (size_t)ctx->nblk)) break;
+        if (!alloc((void**)&ctx->d_pacc, sizeof(unsigned long long) * 2 * (size_t)ctx->nblk)) break;
+        DevState hs{};
+        hs.cone_deg = run->cone_deg;
+        hs.adapt_every = run->adapt_every;
+        const double sh = std::sin(0.5 * run->cone_deg * kPi / 180.0);
+        hs.omc = (float)(2.0 * sh * sh);
+        if (hipMemcpy(ctx->d_st, &hs, sizeof hs, hipMemcpyHostToDevice) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "copy"); break; }
+        if (ctx->demag) {
+            DemagPlan& p = ctx->plan;
+            p.Px = pad_pow2(grid->nx, 2);
+            p.Py = pad_pow2(grid->ny, 1);
+            p.L = p.Px / 2;
+            p.logL = ilog2i(p.L);
+            p.logPy = ilog2i(p.Py);
+            p.S = 3 * grid->nz;
+            p.R = std::max(1, std::min(16, 4096 / p.L));
+            std::vector<float> K;
+            tensor_spectrum(grid->nx, grid->ny, grid->nz, cell->hx, cell->hy, cell->hz, p.Px, p.Py, K);
+            if (!alloc((void**)&p.K, sizeof(float) * K.size())) break;
+            if (hipMemcpy(p.K, K.data(), sizeof(float) * K.size(), hipMemcpyHostToDevice) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "copy"); break; }
+            if (!alloc((void**)&p.X, sizeof(float2) * (size_t)(p.L + 1) * p.S * grid->ny)) break;
+            std::vector<float2> tw(8192);
+            for (int j = 0; j < 8192; ++j) tw[j] = make_float2((float)std::cos(-2.0 * kPi * j / 8192), (float)std::sin(-2.0 * kPi * j / 8192));
+            if (!alloc((void**)&ctx->d_tw, sizeof(float2) * 8192)) break;
+            if (hipMemcpy(ctx->d_tw, tw.data(), sizeof(float2) * 8192, hipMemcpyHostToDevice) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "copy"); break; }
+        }
+        st = init_state(ctx);
+    } while (false);
+    if (st != MMC_OK) {
+        mmc_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return MMC_OK;
+}
+
+mmc_status mmc_set_grains(mmc_ctx* ctx, const uint32_t* grain_of_cell, uint32_t n_grains, const double* easy_axis3,
+                          const double* K1, const double* K2, const double* Tc, double boundary_exchange_scale) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!grain_of_cell || !easy_axis3 || !K1 || !K2 || !Tc || n_grains < 1) return fail(MMC_ERR_ARG, "NULL or empty grain data");
+    if (!(boundary_exchange_scale >= 0) || !std::isfinite(boundary_exchange_scale)) return fail(MMC_ERR_DOMAIN, "bad boundary scale");
+    for (uint32_t k = 0; k < n_grains; ++k) {
+        const double* e = easy_axis3 + 3 * k;
+        if (!(Tc[k] > 0) || !std::isfinite(K1[k]) || !std::isfinite(K2[k]) || !(e[0] * e[0] + e[1] * e[1] + e[2] * e[2] > 0))
+            return fail(MMC_ERR_DOMAIN, "grain %u: invalid constants", k);
+    }
+    std::vector<uint32_t> split(2 * (size_t)ctx->Nc, 0u);
+    for (long long p = 0; p < ctx->N; ++p) {
+        const uint32_t k = grain_of_cell[p];
+        if (k >= n_grains) return fail(MMC_ERR_ARG, "grain id %u of cell %lld >= n_grains", k, p);
+        const int x = (int)(p % ctx->g.nx), y = (int)((p / ctx->g.nx) % ctx->g.ny), z = (int)(p / ((long long)ctx->g.nx * ctx->g.ny));
+        const int c = (x + y + z) & 1;
+        split[(size_t)c * ctx->Nc + ((size_t)z * ctx->g.ny + y) * ctx->hw + (x >> 1)] = k;
+    }
+    ctx->nclass = (int)n_grains;
+    ctx->ea.assign(easy_axis3, easy_axis3 + 3 * (size_t)n_grains);
+    ctx->K1.assign(K1, K1 + n_grains); ctx->K2.assign(K2, K2 + n_grains); ctx->Tc.assign(Tc, Tc + n_grains);
+    ctx->bscale = boundary_exchange_scale;
+    ctx->has_classes = true;
+    if (!ctx->d_cid) HIPCK(hipMalloc(&ctx->d_cid, sizeof(uint32_t) * 2 * (size_t)ctx->Nc));
+    HIPCK(hipMemcpy(ctx->d_cid, split.data(), sizeof(uint32_t) * split.size(), hipMemcpyHostToDevice));
+    update_args(ctx);
+    s = upload_classes(ctx);
+    if (s != MMC_OK) return s;
+    return init_state(ctx);
+}
+
+mmc_status mmc_set_field(mmc_ctx* ctx, const double mu0H_tesla[3]) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!mu0H_tesla) return fail(MMC_ERR_ARG, "NULL field");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(mu0H_tesla[k])) return fail(MMC_ERR_DOMAIN, "field must be finite");
+    for (int k = 0; k < 3; ++k) ctx->run.B[k] = mu0H_tesla[k];
+    update_args(ctx);
+    return MMC_OK;
+}
+
+mmc_status mmc_set_temperature(mmc_ctx* ctx, double T) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!(T > 0) || !std::isfinite(T)) return fail(MMC_ERR_DOMAIN, "temperature must be > 0");
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    ctx->run.T = T;
+    update_args(ctx);
+    return upload_classes(ctx);
+}
+
+mmc_status mmc_set_m(mmc_ctx* ctx, const float* m, int on_device) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!m) return fail(MMC_ERR_ARG, "NULL state");
+    std::vector<float> host;
+    const float* hm = m;
+    if (on_device) {
+        host.resize(3 * (size_t)ctx->N);
+        HIPCK(hipMemcpyAsync(host.data(), m, sizeof(float) * host.size(), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCK(hipStreamSynchronize(ctx->stream));
+        hm = host.data();
+    }
+    for (long long p = 0; p < ctx->N; ++p) {
+        const double a = hm[p], b = hm[ctx->N + p], c = hm[2 * ctx->N + p];
+        const double q = a * a + b * b + c * c;
+        if (!(q > 0) || !std::isfinite(q)) return fail(MMC_ERR_DOMAIN, "cell %lld: |m| must be finite and > 0", p);
+    }
+    if (!ctx->d_nat) HIPCK(hipMalloc(&ctx->d_nat, sizeof(float) * 3 * (size_t)ctx->N));
+    HIPCK(hipMemcpyAsync(ctx->d_nat, m, sizeof(float) * 3 * (size_t)ctx->N,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(launch_to_split(ctx->args, ctx->d_nat, ctx->d_m, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MMC_OK;
+}
+
+mmc_status mmc_get_m(mmc_ctx* ctx, float* out, int on_device) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!out) return fail(MMC_ERR_ARG, "NULL output");
+    if (on_device) {
+        HIPCK(launch_from_split(ctx->args, ctx->d_m, out, ctx->stream));
+    } else {
+        if (!ctx->d_nat) HIPCK(hipMalloc(&ctx->d_nat, sizeof(float) * 3 * (size_t)ctx->N));
+        HIPCK(launch_from_split(ctx->args, ctx->d_m, ctx->d_nat, ctx->stream));
+        HIPCK(hipMemcpyAsync(out, ctx->d_nat, sizeof(float) * 3 * (size_t)ctx->N, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MMC_OK;
+}
+
+mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (n < 0) return fail(MMC_ERR_ARG, "negative sweep count");
+    return enqueue_sweeps(ctx, n, nullptr, 0);
+}
+
+mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, double ms_out[5], int32_t launches_out[5]) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (n < 0 || !ms_out || !launches_out) return fail(MMC_ERR_ARG, "bad count or NULL output");
+    LaunchProf prof;
+    const size_t per_sweep = 2 * (ctx->demag ? 3 : 0) + 2 + 1;
+    prof.ev.resize(2 * per_sweep * (size_t)n + 2);
+    mmc_status st = MMC_OK;
+    size_t made = 0;
+    for (; made < prof.ev.size(); ++made)
+        if (hipEventCreate(&prof.ev[made]) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "event creation failed"); break; }
+    if (st == MMC_OK) st = enqueue_sweeps(ctx, n, nullptr, 0, &prof);
+    if (st == MMC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(MMC_ERR_DEVICE, "synchronize failed");
+    for (int k = 0; k < 5; ++k) { ms_out[k] = 0.0; launches_out[k] = 0; }
+    if (st == MMC_OK) {
+        for (size_t i = 0; i < prof.kind.size(); ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, prof.ev[2 * i], prof.ev[2 * i + 1]) != hipSuccess) {
+                st = fail(MMC_ERR_DEVICE, "event timing failed");
+                break;
+            }
+            ms_out[prof.kind[i]] += ms;
+            launches_out[prof.kind[i]] += 1;
+        }
+    }
+    for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(prof.ev[i]);
+    return st;
+}
+
+mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (n < 0 || (n > 0 && !series)) return fail(MMC_ERR_ARG, "bad count or NULL series");
+    if (n == 0) return MMC_OK;
+    if (ctx->series_cap < n) {
+        if (ctx->d_series) HIPCK(hipFree(ctx->d_series));
+        ctx->d_series = nullptr;
+        HIPCK(hipMalloc(&ctx->d_series, sizeof(double) * 5 * (size_t)n));
+        ctx->series_cap = n;
+    }
+    const unsigned long long base = ctx->host_sweep;
+    s = enqueue_sweeps(ctx, n, ctx->d_series, base);
+    if (s != MMC_OK) return s;
+    HIPCK(hipMemcpyAsync(series, ctx->d_series, sizeof(double) * 5 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MMC_OK;
+}
+
+mmc_status mmc_demag_field(mmc_ctx* ctx, float* h_out, int on_device) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!h_out) return fail(MMC_ERR_ARG, "NULL output");
+    if (!ctx->demag) return fail(MMC_ERR_STATE, "demag is off for this context");
+    HIPCK(launch_demag(ctx->args, ctx->plan, ctx->d_m, ctx->d_h, 3, ctx->d_tw, ctx->stream));
+    float* dst = on_device ? h_out : nullptr;
+    if (!on_device) {
+        if (!ctx->d_nat) HIPCK(hipMalloc(&ctx->d_nat, sizeof(float) * 3 * (size_t)ctx->N));
+        dst = ctx->d_nat;
+    }
+    HIPCK(launch_from_split(ctx->args, ctx->d_h, dst, ctx->stream));
+    if (!on_device)
+        HIPCK(hipMemcpyAsync(h_out, dst, sizeof(float) * 3 * (size_t)ctx->N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MMC_OK;
+}
+
+mmc_status mmc_energy(mmc_ctx* ctx, double* E_total, double E_terms[6]) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!E_total && !E_terms) return fail(MMC_ERR_ARG, "NULL outputs");
+    if (ctx->demag) HIPCK(launch_demag(ctx->args, ctx->plan, ctx->d_m, ctx->d_h, 3, ctx->d_tw, ctx->stream));
+    const int blocks = (int)std::min<long long>((ctx->N + 255) / 256, 2048);
+    if (ctx->epart_n < blocks) {
+        if (ctx->d_epart) HIPCK(hipFree(ctx->d_epart));
+        ctx->d_epart = nullptr;
+        HIPCK(hipMalloc(&ctx->d_epart, sizeof(double) * 6 * blocks));
+        ctx->epart_n = blocks;
+    }
+    int nb = 0;
+    HIPCK(launch_energy(ctx->args, ctx->has_classes, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->demag ? ctx->d_h : nullptr,
+                        ctx->d_epart, ctx->stream, &nb));
+    std::vector<double> part(6 * (size_t)nb);
+    HIPCK(hipMemcpyAsync(part.data(), ctx->d_epart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    const double kT = kB * ctx->run.T;
+    double t[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < 6; ++k) t[k] += part[6 * b + k];
+    double tot = 0;
+    for (int k = 0; k < 6; ++k) { t[k] *= kT; tot += t[k]; }
+    if (E_terms) for (int k = 0; k < 6; ++k) E_terms[k] = t[k];
+    if (E_total) *E_total = tot;
+    return MMC_OK;
+}
+
+mmc_status mmc_subsweep(mmc_ctx* ctx, int32_t colour, const float* h_in, uint8_t* acc_out) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (colour != 0 && colour != 1) return fail(MMC_ERR_ARG, "colour must be 0 or 1");
+    if (!acc_out) return fail(MMC_ERR_ARG, "NULL decision output");
+    HIPCK(hipMemsetAsync(acc_out, 255, (size_t)ctx->N, ctx->stream));
+    if (h_in) HIPCK(launch_to_split(ctx->args, h_in, ctx->d_h, ctx->stream));
+    HIPCK(launch_subsweep(ctx->args, ctx->has_classes, h_in != nullptr, ctx->run.lenmove == MMC_LEN_EXACT,
+                          ctx->mat.D0 != 0.0, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, colour, ctx->d_st,
+                          ctx->d_part, ctx->d_pacc, acc_out, ctx->stream, nullptr));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MMC_OK;
+}
+
+mmc_status mmc_get_stats(mmc_ctx* ctx, mmc_stats* out) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!out) return fail(MMC_ERR_ARG, "NULL output");
+    DevState hs{};
+    HIPCK(hipMemcpyAsync(&hs, ctx->d_st, sizeof hs, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    out->sweeps = hs.sweep;
+    out->accepts_window = hs.window;
+    out->cone_deg = hs.cone_deg;
+    out->sigma = ctx->ctab[0].sigma;
+    out->me = std::sqrt(ctx->ctab[0].me2);
+    for (int k = 0; k < 3; ++k) out->m_mean[k] = hs.last[k];
+    out->m2_mean = hs.last[3];
+    out->accepts_last = hs.accepts_last;
+    return MMC_OK;
+}
+
+mmc_status mmc_get_state(mmc_ctx* ctx, uint64_t* sweep, int32_t* cone_deg, uint64_t* accepts_window) {
+    mmc_stats st{};
+    mmc_status s = mmc_get_stats(ctx, &st);
+    if (s != MMC_OK) return s;
+    if (sweep) *sweep = st.sweeps;
+    if (cone_deg) *cone_deg = st.cone_deg;
+    if (accepts_window) *accepts_window = st.accepts_window;
+    return MMC_OK;
+}
+
+mmc_status mmc_set_state(mmc_ctx* ctx, uint64_t sweep, int32_t cone_deg, uint64_t accepts_window) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (cone_deg < 1 || cone_deg > 180) return fail(MMC_ERR_ARG, "cone_deg must be in [1, 180]");
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    DevState hs{};
+    HIPCK(hipMemcpy(&hs, ctx->d_st, sizeof hs, hipMemcpyDeviceToHost));
+    hs.sweep = sweep;
+    hs.window = accepts_window;
+    hs.cone_deg = cone_deg;
+    const double sh = std::sin(0.5 * cone_deg * kPi / 180.0);
+    hs.omc = (float)(2.0 * sh * sh);
+    HIPCK(hipMemcpy(ctx->d_st, &hs, sizeof hs, hipMemcpyHostToDevice));
+    ctx->host_sweep = sweep;
+    return MMC_OK;
+}
+
+mmc_status mmc_sync(mmc_ctx* ctx) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MMC_OK;
+}
+
+// ---------------------------------------------------------------------
+// Batches: every chain's sweeps on a stream of its own, forked from and
+// joined back to one stream, captured once as a HIP graph and replayed.
+// ---------------------------------------------------------------------
+mmc_status mmc_batch_create(mmc_ctx* const* chains, int32_t n, mmc_batch** out) {
+    mmc_ctx* ctx = nullptr;
+    if (!chains || n < 1 || !out) return fail(MMC_ERR_ARG, "need at least one chain");
+    for (int i = 0; i < n; ++i) {
+        if (!chains[i]) return fail(MMC_ERR_ARG, "NULL chain %d", i);
+        if (chains[i]->dead) return fail(MMC_ERR_STATE, "chain %d had a device error", i);
+        if (chains[i]->device != chains[0]->device) return fail(MMC_ERR_ARG, "chains on different devices");
+        for (int j = 0; j < i; ++j)
+            if (chains[j] == chains[i]) return fail(MMC_ERR_ARG, "chain %d listed twice", i);
+    }
+    mmc_batch* b = new (std::nothrow) mmc_batch();
+    if (!b) return fail(MMC_ERR_OOM, "host allocation failed");
+    b->ch.assign(chains, chains + n);
+    HIPCK(hipSetDevice(chains[0]->device));
+    b->streams.resize(n);
+    b->done.resize(n);
+    for (int i = 0; i < n; ++i) {
+        if (hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming) != hipSuccess) {
+            mmc_batch_destroy(b);
+            return fail(MMC_ERR_DEVICE, "stream/event creation failed");
+        }
+    }
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+        mmc_batch_destroy(b);
+        return fail(MMC_ERR_DEVICE, "event creation failed");
+    }
+    *out = b;
+    return MMC_OK;
+}
+
+static void batch_drop_graph(mmc_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_n = -1;
+}
+
+mmc_status mmc_batch_sweep(mmc_batch* b, int32_t n) {
+    mmc_ctx* ctx = nullptr;
+    if (!b) return fail(MMC_ERR_ARG, "NULL batch");
+    if (n < 0) return fail(MMC_ERR_ARG, "negative sweep count");
+    if (n == 0) return MMC_OK;
+    for (auto* c : b->ch)
+        if (c->dead) return fail(MMC_ERR_STATE, "a chain had a device error");
+    HIPCK(hipSetDevice(b->ch[0]->device));
+    bool stale = b->graph_n != n || b->versions.size() != b->ch.size();
+    for (size_t i = 0; !stale && i < b->ch.size(); ++i) stale = b->versions[i] != b->ch[i]->version;
+    hipStream_t s0 = b->ch[0]->stream;
+    if (stale) {
+        batch_drop_graph(b);
+        // a chain's own stream may hold earlier work: order it before the graph
+        for (size_t i = 1; i < b->ch.size(); ++i) HIPCK(hipStreamSynchronize(b->ch[i]->stream));
+        HIPCK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+        HIPCK(hipEventRecord(b->fork, s0));
+        std::vector<hipStream_t> saved(b->ch.size());
+        mmc_status st = MMC_OK;
+        for (size_t i = 0; i < b->ch.size(); ++i) {
+            mmc_ctx* c = b->ch[i];
+            HIPCK(hipStreamWaitEvent(b->streams[i], b->fork, 0));
+            saved[i] = c->stream;
+            c->stream = b->streams[i];
+            const unsigned long long hs = c->host_sweep;
+            st = enqueue_sweeps(c, n, nullptr, 0);
+            c->host_sweep = hs;
+            c->stream = saved[i];
+            if (st != MMC_OK) break;
+            HIPCK(hipEventRecord(b->done[i], b->streams[i]));
+            HIPCK(hipStreamWaitEvent(s0, b->done[i], 0));
+        }
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s0, &g);
+        if (st != MMC_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        HIPCK(e);
+        b->graph = g;
+        HIPCK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_n = n;
+        b->versions.resize(b->ch.size());
+        for (size_t i = 0; i < b->ch.size(); ++i) b->versions[i] = b->ch[i]->version;
+    }
+    HIPCK(hipGraphLaunch(b->exec, s0));
+    for (auto* c : b->ch) c->host_sweep += (unsigned long long)n;
+    return MMC_OK;
+}
+
+mmc_status mmc_batch_sync(mmc_batch* b) {
+    mmc_ctx* ctx = nullptr;
+    if (!b) return fail(MMC_ERR_ARG, "NULL batch");
+    HIPCK(hipSetDevice(b->ch[0]->device));
+    HIPCK(hipStreamSynchronize(b->ch[0]->stream));
+    return MMC_OK;
+}
+
+void mmc_batch_destroy(mmc_batch* b) {
+    if (!b) return;
+    if (!b->ch.empty()) {
+        (void)hipSetDevice(b->ch[0]->device);
+        (void)hipStreamSynchronize(b->ch[0]->stream);
+    }
+    batch_drop_graph(b);
+    for (auto s : b->streams) if (s) (void)hipStreamDestroy(s);
+    for (auto e : b->done) if (e) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal declarations shared by the libmmc sources (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <vector>
+#include "../../include/mmc.h"
+
+namespace mmc {
+
+// Physical constants (SI): kB exact (2019 SI), mu0 = 4 pi 1e-7.
+constexpr double kB = 1.380649e-23;
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+constexpr double kPi = 3.14159265358979323846;
+
+// Per-class (grain) coefficients in units of kT, as the sweep kernel reads them.
+struct alignas(16) ClassCoef {
+    double me2;      // me^2 (double: (m^2 - me^2) is formed in FP64)
+    float la;        // T < Tc: F_l/kT = la (m^2 - me^2)^2
+    float lb, lbc;   // T >= Tc: F_l/kT = lb m^2 + lbc m^4
+    float below;     // 1: T < Tc branch
+    float sigma;     // length-move width
+    float ln1ps;     // ln(1 + sigma)
+    float m0;        // initial length
+    float ex, ey, ez;  // easy axis (unit)
+    float ka1, ka2;  // V K1/kT, V K2/kT
+    float pad;
+};
+static_assert(sizeof(ClassCoef) == 64, "ClassCoef layout");
+
+// Uniform per-chain constants of a colour pass (kT units).
+struct SweepArgs {
+    int nx, ny, nz, hw;          // hw = ceil(nx/2): cells per row and colour
+    long long Nc;                // nz*ny*hw: slots per colour
+    float wx, wy, wz;            // exchange V A0 / (h^2 kT)
+    float cdx, cdy;              // DMI V D0 / (h kT)
+    float bx, by, bz;            // Zeeman V Ms0 (mu0 H) / kT
+    float cdm;                   // demag mu0 V Ms0^2 / kT
+    float bscale;                // exchange scale across grain boundaries
+    uint32_t k0, k1, chain;      // Philox key and chain id
+};
+
+// Device-resident run state: read by the kernels, advanced on the device,
+// so a captured sequence of sweeps can be replayed.
+struct DevState {
+    unsigned long long sweep;        // sweeps completed
+    unsigned long long window;       // accepts since the last cone adaptation
+    unsigned long long accepts_last; // accepts in the last sweep
+    int cone_deg;
+    int adapt_every;
+    float omc;                       // 1 - cos(cone)
+    int pad;
+    double last[4];                  // <mx>, <my>, <mz>, <|m|^2> after the last sweep
+};
+
+// Host-side physics setup (setup.cpp).
+void meanfield(int model, double T, double Tc, double mu, double* me, double* inv_chi);
+ClassCoef class_coef(const mmc_material& mat, double T, double V, double K1, double K2, const double* ea,
+                     double Tc, double sigma_fixed, int nthreads);
+// Demag tensor spectrum K[kx][ky'][q][dz] (kx in [0, Px/2], ky' in [0, Py/2],
+// q = xx,yy,zz,xy,xz,yz, dz in [0,nz)), including the -1/(Px Py) factor.
+void tensor_spectrum(int nx, int ny, int nz, double hx, double hy, double hz, int Px, int Py,
+                     std::vector<float>& K);
+void newell_tensor(double X, double Y, double Z, double hx, double hy, double hz, double out[6]);
+
+// Kernel launchers (kernels.hip).
+struct DemagPlan {
+    int Px, Py, L, S, R, logL, logPy;
+    float2* X;        // [(L+1)][S][ny] complex work buffer
+    float* K;         // tensor spectrum
+};
+hipError_t launch_init(const SweepArgs& a, const ClassCoef* ctab, const uint32_t* cid, float* m, int kind,
+                       float dx, float dy, float dz, hipStream_t s);
+hipError_t launch_to_split(const SweepArgs& a, const float* nat, float* split, hipStream_t s);
+hipError_t launch_from_split(const SweepArgs& a, const float* split, float* nat, hipStream_t s);
+hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h,
+                              int colour_mask, const float2* tw, hipStream_t s);
+hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int colour_mask,
+                        const float2* tw, hipStream_t s);
+hipError_t launch_subsweep(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi,
+                           const ClassCoef* ctab, const uint32_t* cid, float* m, const float* h, int colour,
+                           const DevState* st, double* part, unsigned long long* pacc, uint8_t* acc_out,
+                           hipStream_t s, int* nblk_out);
+int subsweep_blocks(const SweepArgs& a);
+hipError_t launch_finalize(const double* part, const unsigned long long* pacc, int nblk, long long N,
+                           DevState* st, double* series, unsigned long long rec_base, hipStream_t s);
+hipError_t launch_energy(const SweepArgs& a, bool classes, const ClassCoef* ctab, const uint32_t* cid,
+                         const float* m, const float* h, double* part, hipStream_t s, int* nblk_out);
+hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s);
+
+}  // namespace mmc

@@ -1,0 +1,279 @@
+"""Thin ctypes binding of libmmc (include/mmc.h).
+
+Argument marshalling only: every step of the Monte Carlo path runs in the HIP
+library.  The binding refuses to work without the built library (there is no
+CPU fallback).  PyTorch is used only to hand device memory and the current HIP
+stream to the library.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libmmc.so")
+
+MMC_OK, MMC_ERR_ARG, MMC_ERR_DOMAIN, MMC_ERR_OOM, MMC_ERR_DEVICE, MMC_ERR_STATE, MMC_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MMC_MF_LANGEVIN, MMC_MF_BRILLOUIN_HALF = 0, 1
+MMC_LEN_PAPER, MMC_LEN_EXACT = 0, 1
+MMC_DEMAG_OFF, MMC_DEMAG_FP32 = 0, 1
+MUB = 9.2740100783e-24
+
+
+class MMCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+class mmc_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
+
+
+class mmc_cellsize(C.Structure):
+    _fields_ = [("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double)]
+
+
+class mmc_material(C.Structure):
+    _fields_ = [("Ms0", C.c_double), ("A0", C.c_double), ("D0", C.c_double), ("K1", C.c_double),
+                ("K2", C.c_double), ("easy_axis", C.c_double * 3), ("Tc", C.c_double),
+                ("mu_atomic", C.c_double), ("mf", C.c_int32)]
+
+
+class mmc_run(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("chain_id", C.c_uint32), ("cone_deg", C.c_int32),
+                ("adapt_every", C.c_int32), ("sigma_fixed", C.c_double), ("lenmove", C.c_int32),
+                ("demag", C.c_int32), ("refresh_per_sweep", C.c_int32), ("T", C.c_double),
+                ("B", C.c_double * 3), ("init", C.c_int32), ("init_dir", C.c_double * 3)]
+
+
+class mmc_stats(C.Structure):
+    _fields_ = [("sweeps", C.c_uint64), ("accepts_window", C.c_uint64), ("cone_deg", C.c_int32),
+                ("sigma", C.c_double), ("me", C.c_double), ("m_mean", C.c_double * 3),
+                ("m2_mean", C.c_double), ("accepts_last", C.c_uint64)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "mmc_create": (C.c_int, [C.POINTER(mmc_grid), C.POINTER(mmc_cellsize), C.POINTER(mmc_material),
+                             C.POINTER(mmc_run), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mmc_destroy": (None, [C.c_void_p]),
+    "mmc_set_grains": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_double]),
+    "mmc_set_field": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "mmc_set_temperature": (C.c_int, [C.c_void_p, C.c_double]),
+    "mmc_set_m": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "mmc_get_m": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "mmc_sweep": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mmc_sweep_record": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "mmc_sweep_timed": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "mmc_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "mmc_demag_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "mmc_subsweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "mmc_get_stats": (C.c_int, [C.c_void_p, C.POINTER(mmc_stats)]),
+    "mmc_get_state": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
+    "mmc_set_state": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint64]),
+    "mmc_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "mmc_batch_sweep": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mmc_batch_sync": (C.c_int, [C.c_void_p]),
+    "mmc_batch_destroy": (None, [C.c_void_p]),
+    "mmc_sync": (C.c_int, [C.c_void_p]),
+    "mmc_status_str": (C.c_char_p, [C.c_int]),
+    "mmc_last_error": (C.c_char_p, []),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """Load libmmc.so (built by paper_2106_05593_amd/build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            raise ImportError("libmmc.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
+        L = C.CDLL(SO)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != MMC_OK:
+        raise MMCError(status, lib().mmc_last_error().decode())
+
+
+def _current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Chain:
+    """One Markov chain on the GPU (a context of libmmc).
+
+    grid (nx, ny, nz), cell (hx, hy, hz) in m; material constants in SI; T in K;
+    B = mu0*H in tesla.  stream: 'torch' (torch's current stream), None (a
+    library-owned stream) or an integer hipStream_t.
+    """
+
+    def __init__(self, grid, cell, Ms0, A0, K1, Tc, T, D0=0.0, K2=0.0, easy_axis=(0, 0, 1), B=(0, 0, 0),
+                 mf=MMC_MF_BRILLOUIN_HALF, mu=MUB, seed=0, chain_id=0, cone_deg=30, adapt_every=100,
+                 sigma_fixed=0.0, lenmove=MMC_LEN_PAPER, demag=False, refresh_per_sweep=2, init=0,
+                 init_dir=(0, 0, 1), stream=None):
+        self.grid = tuple(int(v) for v in grid)
+        self.N = int(np.prod(self.grid))
+        g = mmc_grid(*self.grid)
+        cs = mmc_cellsize(*[float(v) for v in cell])
+        mat = mmc_material(Ms0=float(Ms0), A0=float(A0), D0=float(D0), K1=float(K1), K2=float(K2),
+                           easy_axis=(C.c_double * 3)(*[float(v) for v in easy_axis]), Tc=float(Tc),
+                           mu_atomic=float(mu), mf=int(mf))
+        run = mmc_run(seed=int(seed), chain_id=int(chain_id), cone_deg=int(cone_deg), adapt_every=int(adapt_every),
+                      sigma_fixed=float(sigma_fixed), lenmove=int(lenmove),
+                      demag=MMC_DEMAG_FP32 if demag else MMC_DEMAG_OFF, refresh_per_sweep=int(refresh_per_sweep),
+                      T=float(T), B=(C.c_double * 3)(*[float(v) for v in B]), init=int(init),
+                      init_dir=(C.c_double * 3)(*[float(v) for v in init_dir]))
+        if stream == "torch":
+            s = _current_stream()
+        elif stream is None:
+            s = C.c_void_p(None)
+        else:
+            s = C.c_void_p(int(stream))
+        h = C.c_void_p()
+        _check(lib().mmc_create(C.byref(g), C.byref(cs), C.byref(mat), C.byref(run), s, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_grains(self, grain_of_cell, easy_axes, K1, K2, Tc, boundary_exchange_scale):
+        gid = np.ascontiguousarray(grain_of_cell, dtype=np.uint32)
+        ea = np.ascontiguousarray(easy_axes, dtype=np.float64).reshape(-1)
+        k1 = np.ascontiguousarray(K1, dtype=np.float64)
+        k2 = np.ascontiguousarray(K2, dtype=np.float64)
+        tc = np.ascontiguousarray(Tc, dtype=np.float64)
+        _check(lib().mmc_set_grains(self._h, gid.ctypes.data, len(tc), ea.ctypes.data, k1.ctypes.data,
+                                    k2.ctypes.data, tc.ctypes.data, float(boundary_exchange_scale)))
+
+    def set_field(self, B):
+        _check(lib().mmc_set_field(self._h, (C.c_double * 3)(*[float(v) for v in B])))
+
+    def set_temperature(self, T):
+        _check(lib().mmc_set_temperature(self._h, float(T)))
+
+    def set_m(self, m):
+        """m: numpy (3, N) float32 (host) or torch CUDA tensor (3, N) float32 (device)."""
+        if hasattr(m, "is_cuda") and m.is_cuda:
+            assert m.dtype.__str__() == "torch.float32" and m.is_contiguous() and m.numel() == 3 * self.N
+            _check(lib().mmc_set_m(self._h, _dptr(m), 1))
+        else:
+            a = np.ascontiguousarray(m, dtype=np.float32).reshape(3, self.N)
+            _check(lib().mmc_set_m(self._h, a.ctypes.data, 0))
+
+    def get_m(self, out=None):
+        if out is not None:
+            assert out.is_cuda and out.is_contiguous() and out.numel() == 3 * self.N
+            _check(lib().mmc_get_m(self._h, _dptr(out), 1))
+            return out
+        a = np.empty((3, self.N), dtype=np.float32)
+        _check(lib().mmc_get_m(self._h, a.ctypes.data, 0))
+        return a
+
+    def sweep(self, n):
+        _check(lib().mmc_sweep(self._h, int(n)))
+
+    def sweep_record(self, n):
+        s = np.zeros((int(n), 5))
+        _check(lib().mmc_sweep_record(self._h, int(n), s.ctypes.data))
+        return s
+
+    def sweep_timed(self, n):
+        """n sweeps with per-kernel HIP-event timing: (ms[5], launches[5]) for
+        demag x-forward, demag y-pass, demag x-inverse, colour pass, end of sweep."""
+        ms = np.zeros(5)
+        cnt = np.zeros(5, dtype=np.int32)
+        _check(lib().mmc_sweep_timed(self._h, int(n), ms.ctypes.data, cnt.ctypes.data))
+        return ms, cnt
+
+    def energy(self):
+        tot = C.c_double()
+        terms = (C.c_double * 6)()
+        _check(lib().mmc_energy(self._h, C.byref(tot), terms))
+        return tot.value, np.array(terms[:])
+
+    def demag_field(self):
+        a = np.empty((3, self.N), dtype=np.float32)
+        _check(lib().mmc_demag_field(self._h, a.ctypes.data, 0))
+        return a
+
+    def subsweep(self, colour, h=None):
+        """One colour pass with frozen field h (torch CUDA (3,N) float32 or None);
+        returns the per-cell decisions as a torch uint8 CUDA tensor."""
+        import torch
+        acc = torch.empty(self.N, dtype=torch.uint8, device="cuda")
+        hp = _dptr(h) if h is not None else C.c_void_p(None)
+        _check(lib().mmc_subsweep(self._h, int(colour), hp, _dptr(acc)))
+        return acc
+
+    def stats(self):
+        s = mmc_stats()
+        _check(lib().mmc_get_stats(self._h, C.byref(s)))
+        return {"sweeps": s.sweeps, "accepts_window": s.accepts_window, "cone_deg": s.cone_deg, "sigma": s.sigma,
+                "me": s.me, "m_mean": list(s.m_mean), "m2_mean": s.m2_mean, "accepts_last": s.accepts_last}
+
+    def get_state(self):
+        sw, cd, win = C.c_uint64(), C.c_int32(), C.c_uint64()
+        _check(lib().mmc_get_state(self._h, C.byref(sw), C.byref(cd), C.byref(win)))
+        return sw.value, cd.value, win.value
+
+    def set_state(self, sweep, cone_deg, window):
+        _check(lib().mmc_set_state(self._h, int(sweep), int(cone_deg), int(window)))
+
+    def sync(self):
+        _check(lib().mmc_sync(self._h))
+
+
+class Batch:
+    """Independent chains advanced together by one HIP graph launch per call."""
+
+    def __init__(self, chains):
+        self.chains = list(chains)
+        arr = (C.c_void_p * len(self.chains))(*[c.handle.value for c in self.chains])
+        h = C.c_void_p()
+        _check(lib().mmc_batch_create(arr, len(self.chains), C.byref(h)))
+        self._h = h
+
+    def sweep(self, n):
+        _check(lib().mmc_batch_sweep(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().mmc_batch_sync(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mmc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,154 @@
+"""GPU parity against the FP64 oracle, through the C-ABI.
+
+Bars (FP32 GPU vs FP64 oracle):
+  * Philox streams and checkerboard indexing: exact (identical uniforms and
+    identical sets of updated cells).
+  * One colour pass from an identical state: identical accept/reject decisions
+    except where the oracle's log-acceptance margin is within DECISION_TOL of 0
+    (FP32 rounding of the proposal and of dF; the bound is derived in the
+    design notes), and accepted states within 2e-6 of |m|.
+  * Demag field: relative L2 error <= 1e-5.
+  * Energy: each term within 2e-6 of the total magnitude.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DECISION_TOL = 2e-4
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def mmc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2106_05593_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def _pair(O, mmc, grid, cell, **kw):
+    okw = dict(kw)
+    for k in ("cone_deg", "adapt_every", "init", "init_dir", "refresh_per_sweep_gpu"):
+        okw.pop(k, None)
+    ch = mmc.Chain(grid, cell, **kw)
+    ref = O.System(grid, cell, **{k: v for k, v in okw.items() if k not in ("lenmove",)},
+                   lenmode=kw.get("lenmove", 0))
+    return ch, ref
+
+
+MAT = dict(Ms0=1e6, A0=1e-11, K1=5e5, Tc=700.0)
+
+
+def _decision_check(O, ch, ref, m0, sweep, colour, cone, h=None):
+    N = m0.shape[1]
+    ch.set_m(m0)
+    ch.set_state(sweep, cone, 0)
+    ht = torch.from_numpy(h.astype(np.float32)).cuda() if h is not None else None
+    acc = ch.subsweep(colour, ht).cpu().numpy().astype(np.int16)
+    m_gpu = ch.get_m()
+    h64 = h.astype(np.float32).astype(np.float64) if h is not None else None
+    m_or, acc_o, margin, mB, _ = ref.subsweep(m0.astype(np.float64), sweep, colour, float(cone), h=h64)
+    mine = acc_o >= 0
+    assert np.array_equal(acc == 255, ~mine), "colour sets differ"
+    mism = mine & (acc != acc_o)
+    worst = np.abs(margin[mism]).max() if mism.any() else 0.0
+    print("colour %d: %d cells, %d accepted, %d mismatches, worst |margin| %.2e"
+          % (colour, mine.sum(), (acc_o == 1).sum(), mism.sum(), worst))
+    assert worst < DECISION_TOL
+    both_acc = mine & (acc == 1) & (acc_o == 1)
+    both_rej = (acc == 0) & (acc_o == 0)
+    scale = np.linalg.norm(m0, axis=0)
+    err = np.abs(m_gpu - mB)[:, both_acc].max(axis=0) / scale[both_acc] if both_acc.any() else np.zeros(1)
+    assert err.max() < 2e-6, err.max()
+    assert np.array_equal(m_gpu[:, both_rej], m0[:, both_rej])
+    assert np.array_equal(m_gpu[:, ~mine], m0[:, ~mine])
+    return mism.sum(), mine.sum()
+
+
+@pytest.mark.parametrize("lenmove", [0, 1])
+def test_init_state_matches_oracle(O, mmc, lenmove):
+    grid, cell = (13, 7, 3), (5e-9,) * 3
+    for T in (300.0, 770.0):
+        ch, ref = _pair(O, mmc, grid, cell, T=T, seed=77, chain_id=5, init=1, lenmove=lenmove, **MAT)
+        m = ch.get_m().astype(np.float64)
+        r = ref.init_state("random")
+        assert np.abs(m - r).max() < 3e-6 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("case", ["plain", "dmi_tilted", "ragged_3d", "exact", "hot"])
+def test_subsweep_decisions_no_demag(O, mmc, case):
+    kw = dict(T=300.0, B=(0.0, 0.0, 0.1), seed=5, chain_id=3, sigma_fixed=0.05, **MAT)
+    grid, cell = (32, 32, 1), (5e-9,) * 3
+    if case == "dmi_tilted":
+        grid, cell = (40, 24, 1), (4e-9, 4e-9, 2e-9)
+        kw.update(D0=1.5e-3, K2=1e5, easy_axis=(0.2, -0.3, 0.9), B=(0.05, -0.02, 0.2), sigma_fixed=0.0, T=350.0)
+    if case == "ragged_3d":
+        grid = (17, 9, 5)
+        kw.update(D0=-2e-3, T=520.0, sigma_fixed=0.0)
+    if case == "exact":
+        kw.update(lenmove=1, T=650.0, sigma_fixed=0.0)
+    if case == "hot":
+        kw.update(T=760.0, sigma_fixed=0.0)
+    ch, ref = _pair(O, mmc, grid, cell, **kw)
+    N = int(np.prod(grid))
+    tot_mis = tot = 0
+    for trial in range(4):
+        c = ref.coeffs()
+        L = c["m0"]
+        m0 = workloads.perturbed_uniform_state(N, seed=10 + trial, L=L, spread=0.4)
+        for colour in (0, 1):
+            a, b = _decision_check(O, ch, ref, m0, sweep=1000 * trial + 7, colour=colour, cone=[30, 5, 90, 180][trial])
+            tot_mis += a
+            tot += b
+    assert tot_mis <= max(2, 1e-3 * tot)
+
+
+def test_subsweep_decisions_with_demag_field(O, mmc):
+    grid, cell = (24, 20, 3), (4e-9, 4e-9, 2e-9)
+    kw = dict(T=450.0, B=(0.0, 0.0, 0.0), seed=9, chain_id=1, demag=True, D0=1e-3, **MAT)
+    ch, ref = _pair(O, mmc, grid, cell, **kw)
+    N = int(np.prod(grid))
+    m0 = workloads.perturbed_uniform_state(N, seed=3, L=ref.coeffs()["m0"], spread=0.5, axis=(1, 0, 0.3))
+    h = ref.demag(m0.astype(np.float64))
+    for colour in (0, 1):
+        _decision_check(O, ch, ref, m0, sweep=42, colour=colour, cone=40, h=h)
+
+
+@pytest.mark.parametrize("grid,cell", [((1, 1, 1), (5e-9,) * 3), ((7, 1, 1), (5e-9,) * 3), ((8, 8, 2), (5e-9,) * 3),
+                                       ((13, 6, 3), (4e-9, 4e-9, 2e-9)), ((33, 17, 4), (3e-9, 5e-9, 2e-9)),
+                                       ((64, 64, 8), (3e-9,) * 3), ((256, 256, 1), (4e-9, 4e-9, 2e-9))])
+def test_demag_field_matches_oracle(O, mmc, grid, cell):
+    N = int(np.prod(grid))
+    ch = mmc.Chain(grid, cell, T=300.0, demag=True, **MAT)
+    m = workloads.random_state(N, seed=N)
+    ch.set_m(m)
+    h = ch.demag_field().astype(np.float64)
+    ref = O.DemagPlan(grid, cell)(m.astype(np.float64))
+    rel = np.linalg.norm(h - ref) / np.linalg.norm(ref)
+    print(grid, "rel L2 %.2e" % rel)
+    assert rel < 1e-5
+
+
+@pytest.mark.parametrize("demag", [False, True])
+def test_energy_matches_oracle(O, mmc, demag):
+    grid, cell = (20, 18, 3), (4e-9, 4e-9, 2e-9)
+    kw = dict(T=420.0, B=(0.01, 0.02, -0.1), D0=1.5e-3, K2=2e5, easy_axis=(0.1, 0.2, 1.0), demag=demag, **MAT)
+    ch, ref = _pair(O, mmc, grid, cell, **kw)
+    N = int(np.prod(grid))
+    m = workloads.random_state(N, seed=2, lmin=0.3, lmax=0.9)
+    ch.set_m(m)
+    E, terms = ch.energy()
+    Eo = ref.energy(m.astype(np.float64))
+    scale = np.abs(Eo).sum()
+    assert np.abs(terms - Eo).max() < 2e-6 * scale, (terms, Eo)
+    assert abs(E - Eo.sum()) < 2e-6 * scale
