@@ -76,6 +76,48 @@ def cpu_baseline(seconds_target=15.0):
             "sample": "%d sweeps of a 256x256x4 section (same cell, material, T, field, demag on), %.1f s" % (n, t)}
 
 
+def batched_leg(n_chains=64, sweeps=100, seed=0):
+    """Independent chains of uneven size, T and field: one HIP-graph launch per
+    call (batched) against the same chains run one after another (plain)."""
+    import torch
+    from paper_2106_05593_amd import Batch, Chain
+    mat = workloads.BASE_MATERIAL
+    params = workloads.batch_chain_params(n_chains, seed)
+
+    def make():
+        return [Chain(p["grid"], (5e-9,) * 3, Ms0=mat["Ms0"], A0=mat["A0"], K1=mat["K1"], Tc=mat["Tc"], T=p["T"],
+                      B=p["B"], mf=mat["mf"], mu=mat["mu"], demag=True, adapt_every=100, seed=seed,
+                      chain_id=p["chain_id"], init=0) for p in params]
+    chains = make()
+    cells = sum(int(np.prod(p["grid"])) for p in params)
+    for c in chains:                                   # warm-up, one at a time
+        c.sweep(2)
+    for c in chains:
+        c.sync()
+    t0 = time.perf_counter()
+    for c in chains:
+        c.sweep(sweeps)
+    for c in chains:
+        c.sync()
+    t_plain = time.perf_counter() - t0
+    b = Batch(chains)
+    b.sweep(sweeps)                                    # captures the graph (first call)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(sweeps)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    for c in chains:
+        c.close()
+    scale = 1000.0 / sweeps                            # chains of 1000 sweeps each
+    return {"chains": n_chains, "cells": cells, "timed_sweeps_per_chain": sweeps,
+            "chains_per_s_batched": n_chains / (t_batch * scale), "chains_per_s_plain": n_chains / (t_plain * scale),
+            "cell_updates_per_s_batched": cells * sweeps / t_batch, "cell_updates_per_s_plain": cells * sweeps / t_plain,
+            "speedup": t_plain / t_batch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,15 +125,28 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+        return
+
     from paper_2106_05593_amd import Chain
 
-    torch.cuda.set_device(0)
     wl = workloads.WORKLOADS["loop_1024x1024x4"]
     mat = workloads.BASE_MATERIAL
     grid = wl["grid"]
@@ -124,7 +179,7 @@ def main():
     ach = per_kernel[dom]["GBs"]
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
-    sweep_bytes = sum(algorithmic_bytes(grid, True, n) * cnt[k] for k, n in enumerate(KINDS)) / args.steps
+    sweep_bytes = sum(algorithmic_bytes(grid, True, n) * int(cnt[k]) for k, n in enumerate(KINDS)) / args.steps
     out = {
         "metric": "MC cell-updates/s at 1024x1024x4 w/ demag; batched chains/s vs plain, FP32",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -135,6 +190,9 @@ def main():
         "roofline": roofline,
         "kernels": per_kernel,
     }
+    if not args.no_batched:
+        print("bench: batched chains leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -65,7 +65,7 @@ typedef enum {
     MMC_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
 } mmc_status;
 
-typedef struct { int32_t nx, ny, nz; } mmc_grid;          /* each >= 1, nx,ny <= 4096, nz <= 8 with demag */
+typedef struct { int32_t nx, ny, nz; } mmc_grid;          /* each >= 1; nx, ny <= 2048; N <= 2^28; nz <= 8 with demag */
 typedef struct { double hx, hy, hz; } mmc_cellsize;       /* metres, > 0 */
 
 /* Mean-field model behind me(T) and chi_par(T). */
@@ -151,7 +151,7 @@ mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series);
  * context's stream before and after every kernel launch; synchronises and
  * returns the summed device time (ms) and the launch count per kernel kind:
  * 0 demag x-forward FFT, 1 demag y-pass (FFT, layer mixing, inverse FFT),
- * 2 demag x-inverse FFT, 3 colour pass, 4 end-of-sweep reduction. */
+ * 2 demag x-inverse FFT, 3 colour pass, 4 end-of-sweep statistics. */
 mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, double ms_out[5], int32_t launches_out[5]);
 
 /* Total free energy (J) and its split {exchange, DMI, anisotropy, Zeeman,

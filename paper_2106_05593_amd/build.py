@@ -2,32 +2,41 @@
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libmmc.so")
-SOURCES = ["csrc/api.cpp", "csrc/setup.cpp", "csrc/kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# (source, extra defines, object name); the y pass is compiled once per layer count
+UNITS = [("csrc/api.cpp", [], "api.o"), ("csrc/setup.cpp", [], "setup.o"), ("csrc/kernels.hip", [], "kernels.o"), ("csrc/sweep.hip", [], "sweep.o"),
+         ("csrc/demag.hip", [], "demag.o")] + \
+        [("csrc/ypass.hip", ["-DMMC_NZ=%d" % k], "ypass_nz%d.o" % k) for k in range(1, 9)]
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
-              # packed FP32 instructions stay off (they are formed only from plain float code anyway)
+              # packed FP32 instructions stay off
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
               "-I", os.path.join(ROOT, "include")]
-    for src in SOURCES:
-        path = os.path.join(HERE, src)
-        obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [HIPCC] + common + lang + ["-c", path, "-o", obj]
+
+    def compile_unit(u):
+        src, defs, obj = u
+        out = os.path.join(build_dir, obj)
+        cmd = [HIPCC] + common + defs + ["-x", "hip", "-c", os.path.join(HERE, src), "-o", out]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr))
+        return out
+
+    workers = max(1, min(len(UNITS), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(compile_unit, UNITS))
     cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", "-o", SO + ".tmp"] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)

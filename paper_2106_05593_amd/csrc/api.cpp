@@ -69,9 +69,8 @@ struct mmc_ctx {
     float* d_h = nullptr;        // [2][3][Nc] colour-split demag field
     float* d_nat = nullptr;      // 3N natural staging
     DevState* d_st = nullptr;
-    double* d_part = nullptr;    // [2][nblk][4]
-    unsigned long long* d_pacc = nullptr;
-    int nblk = 0;
+    SweepAccum* d_acc = nullptr; // per-sweep statistics accumulators
+    int fp_shift = 0;            // fixed-point scale of the accumulators
     double* d_epart = nullptr;
     int epart_n = 0;
     double* d_series = nullptr;
@@ -169,14 +168,13 @@ static mmc_status enqueue_sweeps(mmc_ctx* ctx, int n, double* series, unsigned l
                 }
             }
             HIPCK(mark(-1));
-            HIPCK(launch_subsweep(ctx->args, ctx->has_classes, ctx->demag, ctx->run.lenmove == MMC_LEN_EXACT,
-                                  ctx->mat.D0 != 0.0, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, c, ctx->d_st,
-                                  ctx->d_part + (size_t)c * 4 * ctx->nblk, ctx->d_pacc + (size_t)c * ctx->nblk,
-                                  nullptr, ctx->stream, nullptr));
+            HIPCK(launch_pass(ctx->args, ctx->has_classes, ctx->demag, ctx->run.lenmove == MMC_LEN_EXACT,
+                              ctx->mat.D0 != 0.0, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, c, ctx->d_st, ctx->d_acc,
+                              ctx->fp_shift, nullptr, ctx->stream));
             HIPCK(mark(3));
         }
         HIPCK(mark(-1));
-        HIPCK(launch_finalize(ctx->d_part, ctx->d_pacc, ctx->nblk, ctx->N, ctx->d_st, series, rec_base, ctx->stream));
+        HIPCK(launch_end_sweep(ctx->d_acc, ctx->fp_shift, ctx->N, ctx->d_st, series, rec_base, ctx->stream));
         HIPCK(mark(4));
     }
     ctx->host_sweep += (unsigned long long)n;
@@ -211,7 +209,7 @@ void mmc_destroy(mmc_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    void* bufs[] = {ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, ctx->d_nat, ctx->d_st, ctx->d_part, ctx->d_pacc,
+    void* bufs[] = {ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, ctx->d_nat, ctx->d_st, ctx->d_acc,
                     ctx->d_epart, ctx->d_series, ctx->plan.X, ctx->plan.K, ctx->d_tw};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -223,7 +221,8 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
                       void* hip_stream, mmc_ctx** out) {
     mmc_ctx* ctx = nullptr;
     if (!grid || !cell || !mat || !run || !out) return fail(MMC_ERR_ARG, "NULL argument");
-    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || grid->nx > 4096 || grid->ny > 2048 || grid->nz > 4096)
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || grid->nx > 2048 || grid->ny > 2048 || grid->nz > 4096 ||
+        (long long)grid->nx * grid->ny * grid->nz > (1LL << 28))
         return fail(MMC_ERR_ARG, "grid %d x %d x %d out of range", grid->nx, grid->ny, grid->nz);
     if (!(cell->hx > 0 && cell->hy > 0 && cell->hz > 0) || !std::isfinite(cell->hx * cell->hy * cell->hz))
         return fail(MMC_ERR_DOMAIN, "cell sizes must be positive");
@@ -247,8 +246,8 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
     if (run->demag) {
         if (grid->nz > 8) return fail(MMC_ERR_UNSUPPORTED, "demag needs nz <= 8");
         const int Py = pad_pow2(grid->ny, 1);
-        const int bins = Py <= 256 ? 1 : Py / 256;
-        if (3 * grid->nz * bins > 96) return fail(MMC_ERR_UNSUPPORTED, "demag: 3*nz*max(1,Py/256) must be <= 96");
+        if (3 * grid->nz * ypass_E(grid->nz, Py) > 96)
+            return fail(MMC_ERR_UNSUPPORTED, "demag: padded ny %d with nz %d exceeds the y-pass register budget", Py, grid->nz);
     }
 
     ctx = new (std::nothrow) mmc_ctx();
@@ -290,9 +289,13 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
         if (!alloc((void**)&ctx->d_h, msz)) break;
         if (hipMemset(ctx->d_h, 0, msz) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "memset"); break; }
         if (!alloc((void**)&ctx->d_st, sizeof(DevState))) break;
-        ctx->nblk = subsweep_blocks(ctx->args);
-        if (!alloc((void**)&ctx->d_part, sizeof(double) * 8 * (size_t)ctx->nblk)) break;
-        if (!alloc((void**)&ctx->d_pacc, sizeof(unsigned long long) * 2 * (size_t)ctx->nblk)) break;
+        if (!alloc((void**)&ctx->d_acc, sizeof(SweepAccum))) break;
+        if (hipMemset(ctx->d_acc, 0, sizeof(SweepAccum)) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "memset"); break; }
+        {   // fixed point with headroom for |m| <= 4 summed over N cells: N * 16 * 2^shift <= 2^60
+            int lg = 0;
+            while ((1LL << lg) < ctx->N) ++lg;
+            ctx->fp_shift = 56 - lg;
+        }
         DevState hs{};
         hs.cone_deg = run->cone_deg;
         hs.adapt_every = run->adapt_every;
@@ -307,7 +310,6 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
             p.logL = ilog2i(p.L);
             p.logPy = ilog2i(p.Py);
             p.S = 3 * grid->nz;
-            p.R = std::max(1, std::min(16, 4096 / p.L));
             std::vector<float> K;
             tensor_spectrum(grid->nx, grid->ny, grid->nz, cell->hx, cell->hy, cell->hz, p.Px, p.Py, K);
             if (!alloc((void**)&p.K, sizeof(float) * K.size())) break;
@@ -433,7 +435,7 @@ mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, double ms_out[5], int32_t la
     if (s != MMC_OK) return s;
     if (n < 0 || !ms_out || !launches_out) return fail(MMC_ERR_ARG, "bad count or NULL output");
     LaunchProf prof;
-    const size_t per_sweep = 2 * (ctx->demag ? 3 : 0) + 2 + 1;
+    const size_t per_sweep = 2 * (ctx->demag ? 3 : 0) + 3;
     prof.ev.resize(2 * per_sweep * (size_t)n + 2);
     mmc_status st = MMC_OK;
     size_t made = 0;
@@ -530,9 +532,9 @@ mmc_status mmc_subsweep(mmc_ctx* ctx, int32_t colour, const float* h_in, uint8_t
     if (!acc_out) return fail(MMC_ERR_ARG, "NULL decision output");
     HIPCK(hipMemsetAsync(acc_out, 255, (size_t)ctx->N, ctx->stream));
     if (h_in) HIPCK(launch_to_split(ctx->args, h_in, ctx->d_h, ctx->stream));
-    HIPCK(launch_subsweep(ctx->args, ctx->has_classes, h_in != nullptr, ctx->run.lenmove == MMC_LEN_EXACT,
-                          ctx->mat.D0 != 0.0, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, colour, ctx->d_st,
-                          ctx->d_part, ctx->d_pacc, acc_out, ctx->stream, nullptr));
+    HIPCK(launch_pass(ctx->args, ctx->has_classes, h_in != nullptr, ctx->run.lenmove == MMC_LEN_EXACT,
+                      ctx->mat.D0 != 0.0, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, colour, ctx->d_st, nullptr,
+                      ctx->fp_shift, acc_out, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
     return MMC_OK;
 }

@@ -1,0 +1,78 @@
+// Demag refresh launches: x-direction FFT kernels and the dispatcher of the
+// three stages (kernels and FFT engine in demag_fft.h; the y pass of each
+// layer count is compiled in its own unit, ypass.hip).
+#include "demag_fft.h"
+
+namespace mmc {
+
+// y-pass launchers instantiated in ypass.hip (one unit per layer count)
+extern template hipError_t launch_ypass_nz<1>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<2>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<3>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<4>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<5>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<6>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<7>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<8>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+
+int ypass_E(int nz, int Py) { return y_E(nz, Py); }
+
+template <int L>
+static hipError_t launch_x_L(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int mask,
+                             const float2* tw, hipStream_t s) {
+    constexpr int R = x_R(L);
+    const int ntiles = (a.ny + R - 1) / R;
+    constexpr size_t sh = x_lds(L, x_RPT(L));
+    if (stage == 0)
+        hipLaunchKernelGGL(k_xfwd<L>, dim3(ntiles * p.S), dim3(256), sh, s, a, p.S, ntiles, m, p.X, tw);
+    else
+        hipLaunchKernelGGL(k_xinv<L>, dim3(ntiles * p.S), dim3(256), sh, s, a, p.S, ntiles, (const float2*)p.X, h,
+                           mask, tw);
+    return hipGetLastError();
+}
+
+static hipError_t launch_x(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int mask,
+                           const float2* tw, hipStream_t s) {
+    switch (p.L) {
+        case 1: return launch_x_L<1>(stage, a, p, m, h, mask, tw, s);
+        case 2: return launch_x_L<2>(stage, a, p, m, h, mask, tw, s);
+        case 4: return launch_x_L<4>(stage, a, p, m, h, mask, tw, s);
+        case 8: return launch_x_L<8>(stage, a, p, m, h, mask, tw, s);
+        case 16: return launch_x_L<16>(stage, a, p, m, h, mask, tw, s);
+        case 32: return launch_x_L<32>(stage, a, p, m, h, mask, tw, s);
+        case 64: return launch_x_L<64>(stage, a, p, m, h, mask, tw, s);
+        case 128: return launch_x_L<128>(stage, a, p, m, h, mask, tw, s);
+        case 256: return launch_x_L<256>(stage, a, p, m, h, mask, tw, s);
+        case 512: return launch_x_L<512>(stage, a, p, m, h, mask, tw, s);
+        case 1024: return launch_x_L<1024>(stage, a, p, m, h, mask, tw, s);
+        case 2048: return launch_x_L<2048>(stage, a, p, m, h, mask, tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h,
+                              int colour_mask, const float2* tw, hipStream_t s) {
+    if (stage == 0 || stage == 2) return launch_x(stage, a, p, m, h, colour_mask, tw, s);
+    switch (a.nz) {
+        case 1: return launch_ypass_nz<1>(a, p, tw, s);
+        case 2: return launch_ypass_nz<2>(a, p, tw, s);
+        case 3: return launch_ypass_nz<3>(a, p, tw, s);
+        case 4: return launch_ypass_nz<4>(a, p, tw, s);
+        case 5: return launch_ypass_nz<5>(a, p, tw, s);
+        case 6: return launch_ypass_nz<6>(a, p, tw, s);
+        case 7: return launch_ypass_nz<7>(a, p, tw, s);
+        case 8: return launch_ypass_nz<8>(a, p, tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int colour_mask,
+                        const float2* tw, hipStream_t s) {
+    for (int st = 0; st < 3; ++st) {
+        hipError_t e = launch_demag_stage(st, a, p, m, h, colour_mask, tw, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace mmc

@@ -1,0 +1,404 @@
+// Demag field h = -N * m by zero-padded FFT convolution (paper Sec. III,
+// Eq. 14) for gfx950: FFT engine and kernel templates.
+//
+// Three launches per refresh:
+//   x forward  rows of nx reals -> Px/2+1 complex bins (Px = padded length) via
+//              a half-length complex FFT of z[n] = x[2n] + i x[2n+1]; with the
+//              colour-split state x[2n] and x[2n+1] are slot n of the two
+//              colour rows.  Output X[(k*S + s)*ny + y], S = 3*nz signals.
+//   y pass     one block per kx: FFT over padded y of all S signals, direct
+//              mixing over layers with the tensor spectrum (all S values of a
+//              bin sit in one thread's registers), inverse FFT, crop.
+//   x inverse  inverse of the first, writing h of the requested colours.
+//
+// FFT engine: mixed-radix Stockham, length N and E elements per thread fixed
+// at compile time, data in registers in the strided layout x[j + T*m]
+// (thread j < T = N/E, m < E).  Each pass is a radix-rho butterfly in
+// registers; passes exchange through LDS; the last pass leaves the result in
+// the same strided layout, so the layer mixing needs no exchange.  Twiddles
+// come from tw[i] = exp(-2 pi i i / TW_N), computed in FP64 on the host.
+#pragma once
+#include "mmc_internal.h"
+
+namespace mmc {
+
+constexpr int TW_N = 8192;
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) { return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+// multiply by exp(-+ i pi/2): -i for the forward transform, +i for the inverse
+template <bool INV> __device__ __forceinline__ float2 rot90(float2 a) {
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// multiply by exp(-+ i theta) given (c, s) = (cos theta, sin theta)
+template <bool INV> __device__ __forceinline__ float2 twc(float2 a, float c, float s) {
+    return INV ? make_float2(a.x * c - a.y * s, a.x * s + a.y * c) : make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+
+// LDS index with one slot of skew every 32 (spreads strided writes over banks)
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+constexpr int lds_len(int n) { return n - 1 + ((n - 1) >> 5) + 1; }
+
+template <bool INV> __device__ __forceinline__ void dft2(float2* a) {
+    const float2 t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+}
+template <bool INV> __device__ __forceinline__ void dft4(float2* a) {
+    const float2 s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+    const float2 s13 = cadd(a[1], a[3]), d13 = rot90<INV>(csub(a[1], a[3]));
+    a[0] = cadd(s02, s13);
+    a[2] = csub(s02, s13);
+    a[1] = cadd(d02, d13);
+    a[3] = csub(d02, d13);
+}
+constexpr float kR2 = 0.70710678118654752440f;
+constexpr float kC8 = 0.92387953251128675613f;   // cos(pi/8)
+constexpr float kS8 = 0.38268343236508977173f;   // sin(pi/8)
+template <bool INV> __device__ __forceinline__ void dft8(float2* a) {
+    float2 e[4] = {a[0], a[2], a[4], a[6]}, o[4] = {a[1], a[3], a[5], a[7]};
+    dft4<INV>(e);
+    dft4<INV>(o);
+    o[1] = twc<INV>(o[1], kR2, kR2);
+    o[2] = rot90<INV>(o[2]);
+    o[3] = twc<INV>(o[3], -kR2, kR2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = cadd(e[k], o[k]);
+        a[k + 4] = csub(e[k], o[k]);
+    }
+}
+template <bool INV> __device__ __forceinline__ void dft16(float2* a) {
+    float2 e[8], o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { e[k] = a[2 * k]; o[k] = a[2 * k + 1]; }
+    dft8<INV>(e);
+    dft8<INV>(o);
+    o[1] = twc<INV>(o[1], kC8, kS8);
+    o[2] = twc<INV>(o[2], kR2, kR2);
+    o[3] = twc<INV>(o[3], kS8, kC8);
+    o[4] = rot90<INV>(o[4]);
+    o[5] = twc<INV>(o[5], -kS8, kC8);
+    o[6] = twc<INV>(o[6], -kR2, kR2);
+    o[7] = twc<INV>(o[7], -kC8, kS8);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        a[k] = cadd(e[k], o[k]);
+        a[k + 8] = csub(e[k], o[k]);
+    }
+}
+template <int R, bool INV> __device__ __forceinline__ void dft(float2* a) {
+    if constexpr (R == 2) dft2<INV>(a);
+    else if constexpr (R == 4) dft4<INV>(a);
+    else if constexpr (R == 8) dft8<INV>(a);
+    else if constexpr (R == 16) dft16<INV>(a);
+}
+
+// One Stockham pass, sub-transform size NSUB -> NSUB*RHO, on NS signals
+// v[S0..S0+NS).  Non-final passes write to LDS (signal s at lds + s*ls);
+// the final pass leaves its outputs in registers.
+template <int N, int E, int RHO, int NSUB, bool INV, bool LAST, int NS, int S0, int S>
+__device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* __restrict__ tw, float2* lds, int ls) {
+    constexpr int T = N / E;
+    constexpr int Q = E / RHO;
+    constexpr int STEP = TW_N / (NSUB * RHO);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = j + q * T;
+        const int k = b & (NSUB - 1);
+        float2 w[RHO];
+        if constexpr (NSUB > 1) {
+#pragma unroll
+            for (int r = 1; r < RHO; ++r) w[r] = tw[r * k * STEP];
+        }
+        const int base = (b - k) * RHO + k;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            float2 a[RHO];
+#pragma unroll
+            for (int r = 0; r < RHO; ++r) {
+                a[r] = v[S0 + s][q + r * Q];
+                if constexpr (NSUB > 1) {
+                    if (r > 0) a[r] = INV ? cmulc(a[r], w[r]) : cmul(a[r], w[r]);
+                }
+            }
+            dft<RHO, INV>(a);
+#pragma unroll
+            for (int r = 0; r < RHO; ++r) {
+                if constexpr (LAST) v[S0 + s][q + r * Q] = a[r];
+                else lds[s * ls + lpad(base + r * NSUB)] = a[r];
+            }
+        }
+    }
+}
+
+template <int N, int E, int NSUB, bool INV, int NS, int S0, int S>
+__device__ __forceinline__ void st_passes(float2 (&v)[S][E], int j, const float2* __restrict__ tw, float2* lds, int ls) {
+    if constexpr (NSUB < N) {
+        constexpr int T = N / E;
+        constexpr int RHO = (N / NSUB) < E ? (N / NSUB) : E;
+        constexpr bool LAST = NSUB * RHO >= N;
+        if constexpr (!LAST) __syncthreads();   // earlier readers of lds are done
+        st_pass<N, E, RHO, NSUB, INV, LAST, NS, S0, S>(v, j, tw, lds, ls);
+        if constexpr (!LAST) {
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int m = 0; m < E; ++m) v[S0 + s][m] = lds[s * ls + lpad(j + T * m)];
+        }
+        st_passes<N, E, NSUB * RHO, INV, NS, S0, S>(v, j, tw, lds, ls);
+    }
+}
+
+// Full length-N transform (unnormalised) of signals v[S0..S0+NS).
+template <int N, int E, bool INV, int NS, int S0, int S>
+__device__ __forceinline__ void st_fft(float2 (&v)[S][E], int j, const float2* __restrict__ tw, float2* lds, int ls) {
+    st_passes<N, E, 1, INV, NS, S0, S>(v, j, tw, lds, ls);
+}
+
+// Blocks are dealt to the 8 XCDs round-robin; renumber them so that
+// consecutive logical blocks (neighbouring rows) share an XCD and its L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int per = nb >> 3, rem = nb & 7, xcd = b & 7, i = b >> 3;
+    return xcd < rem ? xcd * (per + 1) + i : rem * (per + 1) + (xcd - rem) * per + i;
+}
+
+// ---------------------------------------------------------------------
+// Compile-time launch geometry
+// ---------------------------------------------------------------------
+constexpr int x_E(int L) { return L < 8 ? L : (L / 8 > 256 ? L / 256 : 8); }
+constexpr int x_T(int L) { return L / x_E(L); }
+constexpr int x_rows_conc(int L) { return 256 / x_T(L); }
+constexpr size_t x_lds(int L, int rpt) { return (size_t)x_rows_conc(L) * rpt * lds_len(L) * sizeof(float2); }
+// rows per thread: as many (<= 4) as keep a block's LDS within 72 KB
+constexpr int x_RPT(int L) { return x_lds(L, 4) <= 72 * 1024 ? 4 : (x_lds(L, 2) <= 72 * 1024 ? 2 : 1); }
+constexpr int x_R(int L) { return x_rows_conc(L) * x_RPT(L); }
+
+constexpr int y_E(int nz, int Py) {
+    int E = nz <= 4 ? 8 : 4;
+    if (E > Py) E = Py;
+    while (Py / E > 512) E *= 2;
+    return E;
+}
+constexpr int y_NSG(int Py) { return Py <= 2048 ? 3 : 1; }
+
+// ---------------------------------------------------------------------
+// x forward: a block holds R consecutive rows of one signal s.
+// ---------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, const float* __restrict__ m,
+                                              float2* __restrict__ X, const float2* __restrict__ tw) {
+    constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), RPT = x_RPT(L), R = RC * RPT;
+    constexpr int LS = lds_len(L);
+    extern __shared__ float2 lds[];
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int s = lb / ntiles, y0 = (lb - s * ntiles) * R;
+    const int comp = s / a.nz, z = s - comp * a.nz;
+    const int j = threadIdx.x % T, rg = threadIdx.x / T;
+    float2 v[RPT][E];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int y = y0 + rg + RC * i;
+        const int ce = (y + z) & 1;
+        const long long ro = ((long long)z * a.ny + y) * a.hw;
+        const float* me = m + ((long long)ce * 3 + comp) * a.Nc + ro;
+        const float* mo = m + ((long long)(1 - ce) * 3 + comp) * a.Nc + ro;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int n = j + T * q;
+            float2 t = make_float2(0.f, 0.f);
+            if (y < a.ny && n < a.hw) {
+                if (2 * n < a.nx) t.x = me[n];
+                if (2 * n + 1 < a.nx) t.y = mo[n];
+            }
+            v[i][q] = t;
+        }
+    }
+    // row r = rg + RC*i lives at lds + r*LS
+    float2* my = lds + rg * LS;
+    st_fft<L, E, false, RPT, 0, RPT>(v, j, tw, my, RC * LS);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+        for (int q = 0; q < E; ++q) my[i * RC * LS + lpad(j + T * q)] = v[i][q];
+    __syncthreads();
+    // X[k] = A + W^k B, A = (Z[k] + conj Z[L-k])/2, B = (Z[k] - conj Z[L-k])/(2i), W = exp(-i pi/L)
+    constexpr int WSTEP = TW_N / (2 * L);
+    for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
+        const int k = e / R, r = e - k * R, y = y0 + r;
+        if (y >= a.ny) continue;
+        const float2 Zk = lds[r * LS + lpad(k & (L - 1))];
+        const float2 Zr = lds[r * LS + lpad((L - k) & (L - 1))];
+        const float2 A = make_float2(0.5f * (Zk.x + Zr.x), 0.5f * (Zk.y - Zr.y));
+        const float2 B = make_float2(0.5f * (Zk.y + Zr.y), -0.5f * (Zk.x - Zr.x));
+        const float2 WB = cmul(tw[k * WSTEP], B);
+        X[((long long)k * S + s) * a.ny + y] = make_float2(A.x + WB.x, A.y + WB.y);
+    }
+}
+
+// x inverse: mirror of k_xfwd; writes h of colour c when (mask >> c) & 1.
+template <int L>
+__global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, const float2* __restrict__ X,
+                                              float* __restrict__ h, int mask, const float2* __restrict__ tw) {
+    constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), RPT = x_RPT(L), R = RC * RPT;
+    constexpr int LS = lds_len(L);
+    extern __shared__ float2 lds[];
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int s = lb / ntiles, y0 = (lb - s * ntiles) * R;
+    const int comp = s / a.nz, z = s - comp * a.nz;
+    const int j = threadIdx.x % T, rg = threadIdx.x / T;
+    constexpr int WSTEP = TW_N / (2 * L);
+    // Z[k] = A + i B, A = X[k] + conj X[L-k], B = (X[k] - conj X[L-k]) W^-k
+    for (int e = threadIdx.x; e < R * L; e += 256) {
+        const int k = e / R, r = e - k * R, y = y0 + r;
+        float2 Zv = make_float2(0.f, 0.f);
+        if (y < a.ny) {
+            const float2 Xa = X[((long long)k * S + s) * a.ny + y];
+            const float2 Xb = X[((long long)(L - k) * S + s) * a.ny + y];
+            const float2 A = make_float2(Xa.x + Xb.x, Xa.y - Xb.y);
+            const float2 D = make_float2(Xa.x - Xb.x, Xa.y + Xb.y);
+            const float2 B = cmulc(D, tw[k * WSTEP]);
+            Zv = make_float2(A.x - B.y, A.y + B.x);
+        }
+        lds[r * LS + lpad(k)] = Zv;
+    }
+    __syncthreads();
+    float2* my = lds + rg * LS;
+    float2 v[RPT][E];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[i][q] = my[i * RC * LS + lpad(j + T * q)];
+    st_fft<L, E, true, RPT, 0, RPT>(v, j, tw, my, RC * LS);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int y = y0 + rg + RC * i;
+        if (y >= a.ny) continue;
+        const int ce = (y + z) & 1;
+        const long long ro = ((long long)z * a.ny + y) * a.hw;
+        float* he = h + ((long long)ce * 3 + comp) * a.Nc + ro;
+        float* ho = h + ((long long)(1 - ce) * 3 + comp) * a.Nc + ro;
+        const bool we = (mask >> ce) & 1, wo = (mask >> (1 - ce)) & 1;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int n = j + T * q;
+            if (n >= a.hw) continue;
+            if (we && 2 * n < a.nx) he[n] = v[i][q].x;
+            if (wo && 2 * n + 1 < a.nx) ho[n] = v[i][q].y;
+        }
+    }
+}
+
+// Forward or inverse FFT of all S signals in groups of NSG through LDS.
+template <int PY, int E, bool INV, int NSG, int G, int S>
+__device__ __forceinline__ void y_groups(float2 (&v)[S][E], int j, const float2* __restrict__ tw, float2* lds, int ls) {
+    if constexpr (G < S) {
+        st_fft<PY, E, INV, NSG, G, S>(v, j, tw, lds, ls);
+        y_groups<PY, E, INV, NSG, G + NSG, S>(v, j, tw, lds, ls);
+    }
+}
+
+// y pass: one block per kx, T = PY/E threads; thread j owns bins j + T*q.
+template <int NZ, int PY>
+__global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2* __restrict__ X,
+                                                            const float* __restrict__ K,
+                                                            const float2* __restrict__ tw) {
+    constexpr int S = 3 * NZ, E = y_E(NZ, PY), T = PY / E, NSG = y_NSG(PY);
+    constexpr int LS = lds_len(PY);
+    extern __shared__ float2 lds[];
+    const int kx = blockIdx.x;
+    const int j = threadIdx.x;
+    const int ny = a.ny;
+    float2 v[S][E];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const float2* src = X + ((long long)kx * S + s) * ny;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int y = j + T * q;
+            v[s][q] = y < ny ? src[y] : make_float2(0.f, 0.f);
+        }
+    }
+    y_groups<PY, E, false, NSG, 0, S>(v, j, tw, lds, LS);
+    // direct mixing over layers: H_i(z) = sum_z' sum_j K_ij(z - z') M_j(z')
+    constexpr int HP = PY / 2;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int ky = j + T * q;
+        const int kyp = ky <= HP ? ky : PY - ky;
+        const float sy = ky <= HP ? 1.0f : -1.0f;
+        const float* Kp = K + ((long long)kx * (HP + 1) + kyp) * 6 * NZ;
+        float2 H[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) H[s] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int zo = 0; zo < NZ; ++zo) {
+#pragma unroll
+            for (int zi = 0; zi < NZ; ++zi) {
+                const int dz = zo - zi, adz = dz >= 0 ? dz : -dz;
+                const float sz = dz >= 0 ? 1.0f : -1.0f;
+                const float kxx = Kp[0 * NZ + adz], kyy = Kp[1 * NZ + adz], kzz = Kp[2 * NZ + adz];
+                const float kxy = sy * Kp[3 * NZ + adz], kxz = sz * Kp[4 * NZ + adz], kyz = sy * sz * Kp[5 * NZ + adz];
+                const float2 Mx = v[0 * NZ + zi][q], My = v[1 * NZ + zi][q], Mz = v[2 * NZ + zi][q];
+                // xz, yz spectra are imaginary: (i k) M = (-k M.y, k M.x)
+                H[0 * NZ + zo].x += kxx * Mx.x + kxy * My.x - kxz * Mz.y;
+                H[0 * NZ + zo].y += kxx * Mx.y + kxy * My.y + kxz * Mz.x;
+                H[1 * NZ + zo].x += kxy * Mx.x + kyy * My.x - kyz * Mz.y;
+                H[1 * NZ + zo].y += kxy * Mx.y + kyy * My.y + kyz * Mz.x;
+                H[2 * NZ + zo].x += -kxz * Mx.y - kyz * My.y + kzz * Mz.x;
+                H[2 * NZ + zo].y += kxz * Mx.x + kyz * My.x + kzz * Mz.y;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) v[s][q] = H[s];
+    }
+    y_groups<PY, E, true, NSG, 0, S>(v, j, tw, lds, LS);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        float2* dst = X + ((long long)kx * S + s) * ny;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int y = j + T * q;
+            if (y < ny) dst[y] = v[s][q];
+        }
+    }
+}
+
+// y-pass launcher for one layer count (instantiated per NZ in its own unit).
+template <int NZ, int PY>
+hipError_t launch_ypass_py(const SweepArgs& a, const DemagPlan& p, const float2* tw, hipStream_t s) {
+    constexpr int E = y_E(NZ, PY);
+    if constexpr (3 * NZ * E <= 96) {
+        constexpr size_t sh = sizeof(float2) * y_NSG(PY) * lds_len(PY);
+        hipLaunchKernelGGL((k_ypass<NZ, PY>), dim3(p.L + 1), dim3(PY / E), sh, s, a, p.X, (const float*)p.K, tw);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;   // rejected at context creation
+    }
+}
+
+template <int NZ>
+hipError_t launch_ypass_nz(const SweepArgs& a, const DemagPlan& p, const float2* tw, hipStream_t s) {
+    switch (p.Py) {
+        case 1: return launch_ypass_py<NZ, 1>(a, p, tw, s);
+        case 2: return launch_ypass_py<NZ, 2>(a, p, tw, s);
+        case 4: return launch_ypass_py<NZ, 4>(a, p, tw, s);
+        case 8: return launch_ypass_py<NZ, 8>(a, p, tw, s);
+        case 16: return launch_ypass_py<NZ, 16>(a, p, tw, s);
+        case 32: return launch_ypass_py<NZ, 32>(a, p, tw, s);
+        case 64: return launch_ypass_py<NZ, 64>(a, p, tw, s);
+        case 128: return launch_ypass_py<NZ, 128>(a, p, tw, s);
+        case 256: return launch_ypass_py<NZ, 256>(a, p, tw, s);
+        case 512: return launch_ypass_py<NZ, 512>(a, p, tw, s);
+        case 1024: return launch_ypass_py<NZ, 1024>(a, p, tw, s);
+        case 2048: return launch_ypass_py<NZ, 2048>(a, p, tw, s);
+        case 4096: return launch_ypass_py<NZ, 4096>(a, p, tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mmc

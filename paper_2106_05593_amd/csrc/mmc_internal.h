@@ -52,6 +52,14 @@ struct DevState {
     double last[4];                  // <mx>, <my>, <mz>, <|m|^2> after the last sweep
 };
 
+// Per-sweep statistics accumulators.  Blocks add fixed-point sums (scale
+// 2^shift) of m_x, m_y, m_z, |m|^2 and the accepted-move count into one of
+// kAccBins bins (one 64-byte line each, so concurrent atomics spread out).
+constexpr int kAccBins = 256;
+struct SweepAccum {
+    long long bin[kAccBins][8];        // 4 sums, accepts, 3 spare
+};
+
 // Host-side physics setup (setup.cpp).
 void meanfield(int model, double T, double Tc, double mu, double* me, double* inv_chi);
 ClassCoef class_coef(const mmc_material& mat, double T, double V, double K1, double K2, const double* ea,
@@ -64,10 +72,13 @@ void newell_tensor(double X, double Y, double Z, double hx, double hy, double hz
 
 // Kernel launchers (kernels.hip).
 struct DemagPlan {
-    int Px, Py, L, S, R, logL, logPy;
+    int Px, Py, L, S;
+    int rpt;          // rows per thread in the x kernels
+    int logL, logPy;
     float2* X;        // [(L+1)][S][ny] complex work buffer
     float* K;         // tensor spectrum
 };
+int ypass_E(int nz, int Py);                    // elements per thread of the y pass
 hipError_t launch_init(const SweepArgs& a, const ClassCoef* ctab, const uint32_t* cid, float* m, int kind,
                        float dx, float dy, float dz, hipStream_t s);
 hipError_t launch_to_split(const SweepArgs& a, const float* nat, float* split, hipStream_t s);
@@ -76,13 +87,12 @@ hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p,
                               int colour_mask, const float2* tw, hipStream_t s);
 hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int colour_mask,
                         const float2* tw, hipStream_t s);
-hipError_t launch_subsweep(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi,
-                           const ClassCoef* ctab, const uint32_t* cid, float* m, const float* h, int colour,
-                           const DevState* st, double* part, unsigned long long* pacc, uint8_t* acc_out,
-                           hipStream_t s, int* nblk_out);
-int subsweep_blocks(const SweepArgs& a);
-hipError_t launch_finalize(const double* part, const unsigned long long* pacc, int nblk, long long N,
-                           DevState* st, double* series, unsigned long long rec_base, hipStream_t s);
+hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, const ClassCoef* ctab,
+                       const uint32_t* cid, float* m, const float* h, int colour, const DevState* st, SweepAccum* acc,
+                       int shift, uint8_t* dec, hipStream_t s);
+hipError_t launch_end_sweep(SweepAccum* acc, int shift, long long N, DevState* st, double* series,
+                            unsigned long long rec_base, hipStream_t s);
+int pass_blocks(const SweepArgs& a, bool classes);
 hipError_t launch_energy(const SweepArgs& a, bool classes, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out);
 hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s);

@@ -4,7 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <map>
+#include <mutex>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "mmc_internal.h"
@@ -265,7 +268,8 @@ static void parallel_for(int n, Fn fn) {
     for (auto& x : th) x.join();
 }
 
-void tensor_spectrum(int nx, int ny, int nz, double hx, double hy, double hz, int Px, int Py, std::vector<float>& K) {
+static void tensor_spectrum_compute(int nx, int ny, int nz, double hx, double hy, double hz, int Px, int Py,
+                                    std::vector<float>& K) {
     const int L = Px / 2, hp = Py / 2;
     K.assign((size_t)(L + 1) * (hp + 1) * 6 * nz, 0.0f);
     std::vector<cd> wx(std::max(1, Px / 2)), wy(std::max(1, Py / 2));
@@ -308,6 +312,24 @@ void tensor_spectrum(int nx, int ny, int nz, double hx, double hy, double hz, in
             });
         }
     }
+}
+
+// Chains of equal grid and cell size share one spectrum: computed once per
+// process and kept (a batch of chains typically repeats a few sizes).
+void tensor_spectrum(int nx, int ny, int nz, double hx, double hy, double hz, int Px, int Py, std::vector<float>& K) {
+    using Key = std::tuple<int, int, int, double, double, double, int, int>;
+    static std::mutex mu;
+    static std::map<Key, std::vector<float>> cache;
+    const Key key{nx, ny, nz, hx, hy, hz, Px, Py};
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) { K = it->second; return; }
+    }
+    tensor_spectrum_compute(nx, ny, nz, hx, hy, hz, Px, Py, K);
+    std::lock_guard<std::mutex> g(mu);
+    if (cache.size() >= 16) cache.erase(cache.begin());
+    cache[key] = K;
 }
 
 }  // namespace mmc

@@ -1,0 +1,70 @@
+"""Parity at the full benchmark size (1024 x 1024 x 4 cells of 5 nm, demag on),
+through the C-ABI, in the launch configuration the benchmark times.
+
+* demag field: sampled cells against the oracle's direct sum over all 4.2 M
+  source cells (relative error per sampled vector <= 1e-5 of the field scale);
+* one colour pass, whole grid: identical decisions except where the oracle's
+  log-acceptance margin is within the FP32 tolerance.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GRID, CELL = (1024, 1024, 4), (5e-9, 5e-9, 5e-9)
+MAT = dict(Ms0=1e6, A0=1e-11, K1=5e5, Tc=700.0)
+
+
+@pytest.fixture(scope="module")
+def chain():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_05593_amd import Chain
+    ch = Chain(GRID, CELL, T=630.0, B=(0, 0, 1.0), demag=True, seed=21, **MAT)
+    yield ch
+    ch.close()
+
+
+def test_demag_sampled_cells(chain):
+    from oracle import oracle as O
+    N = int(np.prod(GRID))
+    m = workloads.perturbed_uniform_state(N, seed=5, L=0.4, spread=0.5)
+    chain.set_m(m)
+    h = chain.demag_field()
+    rng = np.random.default_rng(3)
+    nx, ny, nz = GRID
+    corners = [0, nx - 1, (ny - 1) * nx, N - 1]
+    cells = np.concatenate([corners, rng.integers(0, N, 4)])
+    print("sampled cells", cells.tolist(), flush=True)
+    ref = O.demag_direct_at(GRID, CELL, m.astype(np.float64), cells)
+    scale = np.abs(ref).max()
+    err = np.abs(h[:, cells].T.astype(np.float64) - ref).max()
+    print("max abs error %.3e of field scale %.3e" % (err, scale))
+    assert err < 1e-5 * scale
+
+
+def test_colour_pass_whole_grid(chain):
+    from oracle import oracle as O
+    N = int(np.prod(GRID))
+    ref = O.System(GRID, CELL, T=630.0, B=(0, 0, 1.0), demag=True, seed=21, **MAT)
+    c = ref.coeffs()
+    m = workloads.perturbed_uniform_state(N, seed=9, L=c["me"], spread=0.3)
+    # a smooth synthetic frozen field (input, not computed by either side)
+    x = np.arange(N) % GRID[0]
+    hz = (-0.3 + 0.1 * np.sin(2 * np.pi * x / GRID[0])).astype(np.float32)
+    h = np.stack([0.05 * np.cos(2 * np.pi * x / 97.0), 0.02 * np.ones(N), hz]).astype(np.float32)
+    for colour, sweep in ((0, 123456), (1, 7)):
+        chain.set_m(m)
+        chain.set_state(sweep, 17, 0)
+        acc = chain.subsweep(colour, torch.from_numpy(h).cuda()).cpu().numpy().astype(np.int16)
+        _, acc_o, margin, _, _ = ref.subsweep(m.astype(np.float64), sweep, colour, 17.0, h=h.astype(np.float64))
+        mine = acc_o >= 0
+        assert np.array_equal(acc == 255, ~mine)
+        mism = mine & (acc != acc_o)
+        worst = np.abs(margin[mism]).max() if mism.any() else 0.0
+        print("colour %d: %d cells, %d accepted, %d mismatches, worst |margin| %.2e"
+              % (colour, mine.sum(), (acc_o == 1).sum(), mism.sum(), worst))
+        assert worst < 2e-4

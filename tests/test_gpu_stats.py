@@ -1,0 +1,78 @@
+"""Equilibrium statistics: the FP32 GPU chain and the FP64 oracle chain
+(independent seeds) agree on <m_z>, <|m|^2> within 3 combined standard errors
+(batch means after 20 % burn-in)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MAT = dict(Ms0=1e6, A0=1e-11, K1=5e5, Tc=700.0)
+
+
+def batch_mean_se(x, nb=20):
+    x = x[: len(x) // nb * nb].reshape(nb, -1).mean(axis=1)
+    return x.mean(), x.std(ddof=1) / np.sqrt(nb)
+
+
+def _compare(gpu_series, ora_series, burn):
+    for col, name in ((2, "<mz>"), (3, "<|m|^2>")):
+        g, sg = batch_mean_se(gpu_series[burn:, col])
+        o, so = batch_mean_se(ora_series[burn:, col])
+        z = (g - o) / np.hypot(sg, so)
+        print("%s gpu %.6f +- %.2e  oracle %.6f +- %.2e  z = %.2f" % (name, g, sg, o, so, z))
+        assert abs(z) < 3.0
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2106_05593_amd as p
+    p.lib()
+    return p
+
+
+def test_plain_small_workload(pkg):
+    """32x32x1 cells of 5 nm, 300 K, 0.1 T, fixed 30 deg cone, sigma 0.05, 2000 sweeps."""
+    from oracle import oracle as O
+    kw = dict(T=300.0, B=(0, 0, 0.1), sigma_fixed=0.05, **MAT)
+    n = 2000
+    g = pkg.Chain((32, 32, 1), (5e-9,) * 3, seed=101, adapt_every=0, cone_deg=30, **kw)
+    gs = g.sweep_record(n)
+    o = O.System((32, 32, 1), (5e-9,) * 3, seed=202, **kw)
+    m = o.init_state("uniform")
+    os_, _, _ = o.run(m, n, cone_deg=30, adapt_every=0)
+    _compare(gs, os_, n // 5)
+
+
+@pytest.mark.parametrize("lenmove", [0, 1])
+def test_dmi_film_with_demag(pkg, lenmove):
+    """64x64x1 cells of 4x4x2 nm with DMI and demag, 0.5 Tc, 0.5 T along z."""
+    from oracle import oracle as O
+    kw = dict(T=350.0, B=(0, 0, 0.5), D0=1.5e-3, demag=True, **MAT)
+    n = 1500
+    g = pkg.Chain((64, 64, 1), (4e-9, 4e-9, 2e-9), seed=303, adapt_every=100, lenmove=lenmove, **kw)
+    gs = g.sweep_record(n)
+    o = O.System((64, 64, 1), (4e-9, 4e-9, 2e-9), seed=404, lenmode=lenmove, **kw)
+    m = o.init_state("uniform")
+    os_, _, _ = o.run(m, n, cone_deg=30, adapt_every=100)
+    _compare(gs, os_, n // 5)
+
+
+def test_above_tc_granular(pkg):
+    """Grains with scattered Tc around T, weak exchange across boundaries."""
+    import workloads
+    from oracle import oracle as O
+    grid, cell = (24, 24, 4), (3e-9,) * 3
+    cls, ng = workloads.voronoi_grains(grid, cell, 10e-9, seed=5)
+    ea, K1, K2, Tc = workloads.grain_properties(ng, seed=6)
+    n = 1500
+    g = pkg.Chain(grid, cell, T=690.0, B=(0, 0, 0.3), demag=True, seed=505, adapt_every=100, **MAT)
+    g.set_grains(cls, ea, K1, K2, Tc, 0.1)
+    gs = g.sweep_record(n)
+    o = O.System(grid, cell, T=690.0, B=(0, 0, 0.3), demag=True, seed=606, Ms0=MAT["Ms0"], A0=MAT["A0"],
+                 K1=0.0, Tc=700.0, cls=cls, ea=ea, K1s=K1, K2s=K2, Tcs=Tc, bscale=0.1)
+    m = o.init_state("uniform")
+    os_, _, _ = o.run(m, n, cone_deg=30, adapt_every=100)
+    _compare(gs, os_, n // 5)
