@@ -53,6 +53,28 @@ def algorithmic_bytes(grid, demag, kind):
     return 0
 
 
+TRAFFIC_SOURCES_NOTE = "profiles/loop_1024x1024x4_traffic.json"
+
+
+def counted_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, TRAFFIC_SOURCES_NOTE)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for p in rec["sources"]:
+        fp = os.path.join(ROOT, p)
+        if not os.path.exists(fp):
+            return None
+        h.update(open(fp, "rb").read())
+    if h.hexdigest() != rec["source_sha256"] or kernel not in rec["bytes_per_launch"]:
+        return None
+    return rec["bytes_per_launch"][kernel]["total"]
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle (as it stands) on a 256x256x4 section of the same workload."""
     from oracle import oracle as O
@@ -178,7 +200,7 @@ def main():
     dom = max(per_kernel, key=lambda n: per_kernel[n]["total_ms"])
     ach = per_kernel[dom]["GBs"]
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom), "kernel": dom}
     sweep_bytes = sum(algorithmic_bytes(grid, True, n) * int(cnt[k]) for k, n in enumerate(KINDS)) / args.steps
     out = {
         "metric": "MC cell-updates/s at 1024x1024x4 w/ demag; batched chains/s vs plain, FP32",

@@ -198,6 +198,8 @@ __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, co
     const int s = lb / ntiles, y0 = (lb - s * ntiles) * R;
     const int comp = s / a.nz, z = s - comp * a.nz;
     const int j = threadIdx.x % T, rg = threadIdx.x / T;
+    // zero padding: hw <= L/2 (L >= 2), so slots n >= L/2 are zero
+    constexpr int QH = E > 1 ? E / 2 : 1;
     float2 v[RPT][E];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, co
         for (int q = 0; q < E; ++q) {
             const int n = j + T * q;
             float2 t = make_float2(0.f, 0.f);
-            if (y < a.ny && n < a.hw) {
+            if (q < QH && y < a.ny && n < a.hw) {
                 if (2 * n < a.nx) t.x = me[n];
                 if (2 * n + 1 < a.nx) t.y = mo[n];
             }
@@ -283,8 +285,9 @@ __global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, co
         float* he = h + ((long long)ce * 3 + comp) * a.Nc + ro;
         float* ho = h + ((long long)(1 - ce) * 3 + comp) * a.Nc + ro;
         const bool we = (mask >> ce) & 1, wo = (mask >> (1 - ce)) & 1;
+        constexpr int QH = E > 1 ? E / 2 : 1;   // slots n < hw <= L/2 only
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
+        for (int q = 0; q < QH; ++q) {
             const int n = j + T * q;
             if (n >= a.hw) continue;
             if (we && 2 * n < a.nx) he[n] = v[i][q].x;
@@ -313,6 +316,9 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
     const int kx = blockIdx.x;
     const int j = threadIdx.x;
     const int ny = a.ny;
+    // zero padding: ny <= PY/2, so the upper half of each thread's strided
+    // registers (y >= PY/2) is zero on input and not needed on output
+    constexpr int QH = E > 1 ? E / 2 : 1;
     float2 v[S][E];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -320,7 +326,7 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             const int y = j + T * q;
-            v[s][q] = y < ny ? src[y] : make_float2(0.f, 0.f);
+            v[s][q] = (q < QH && y < ny) ? src[y] : make_float2(0.f, 0.f);
         }
     }
     y_groups<PY, E, false, NSG, 0, S>(v, j, tw, lds, LS);
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
     for (int s = 0; s < S; ++s) {
         float2* dst = X + ((long long)kx * S + s) * ny;
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
+        for (int q = 0; q < QH; ++q) {
             const int y = j + T * q;
             if (y < ny) dst[y] = v[s][q];
         }

@@ -32,8 +32,8 @@ __device__ __forceinline__ bool cell_move(const SweepArgs& a, const ClassCoef& C
     const float u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
     const double qAd = (double)ax * ax + (double)ay * ay + (double)az * az;
     const float qA = (float)qAd;
-    const float len = sqrtf(qA);
-    const float inv = 1.0f / len;
+    const float inv = __builtin_amdgcn_rsqf(qA);     // hardware 1/sqrt, ~1 ulp
+    const float len = qA * inv;
     const float nx_ = ax * inv, ny_ = ay * inv, nz_ = az * inv;
     // 1) rotation uniform on the cap of half-angle theta_c
     const float t = u0 * omc;
@@ -42,16 +42,16 @@ __device__ __forceinline__ bool cell_move(const SweepArgs& a, const ClassCoef& C
     sincospif(2.0f * u1, &sp, &cp);
     // orthonormal frame of the current direction (Duff et al., JCGT 2017)
     const float sg = copysignf(1.0f, nz_);
-    const float ia = -1.0f / (sg + nz_);
+    const float ia = -__builtin_amdgcn_rcpf(sg + nz_);   // |sg + nz| >= 1
     const float ib = nx_ * ny_ * ia;
     const float e1x = 1.0f + sg * nx_ * nx_ * ia, e1y = sg * ib, e1z = -sg * nx_;
     const float e2x = ib, e2y = sg + ny_ * ny_ * ia, e2z = -ny_;
     const float dxr = cp * e1x + sp * e2x, dyr = cp * e1y + sp * e2y, dzr = cp * e1z + sp * e2z;
     const float nbx = ct * nx_ + stt * dxr, nby = ct * ny_ + stt * dyr, nbz = ct * nz_ + stt * dzr;
-    // 2) length change
-    float fm1, lnf;
-    if (EXACT) { lnf = (2.0f * u2 - 1.0f) * C.ln1ps; fm1 = expm1f(lnf); }
-    else { fm1 = C.sigma * (2.0f * u2 - 1.0f); lnf = log1pf(fm1); }
+    // 2) length change (logarithms in base 2 with the hardware log2/exp2)
+    float fm1, l2f;
+    if (EXACT) { l2f = (2.0f * u2 - 1.0f) * C.ln1ps * 1.44269504088896341f; fm1 = __builtin_amdgcn_exp2f(l2f) - 1.0f; }
+    else { fm1 = C.sigma * (2.0f * u2 - 1.0f); l2f = __builtin_amdgcn_logf(1.0f + fm1); }
     const float Lb = (1.0f + fm1) * len;
     const float bx = Lb * nbx, by = Lb * nby, bz = Lb * nbz;
     const float Dx = bx - ax, Dy = by - ay, Dz = bz - az;
@@ -78,9 +78,9 @@ __device__ __forceinline__ bool cell_move(const SweepArgs& a, const ClassCoef& C
         else dF += dq * (C.lb + C.lbc * (2.0f * qA + dq));
     }
     if (DMG) dF -= a.cdm * (Dx * hx + Dy * hy + Dz * hz);   // frozen demag field (Eq. 14)
-    // 4) accept with min{1, (mB/mA)^k exp(-dF/kT)} (Eq. 5)
+    // 4) accept with min{1, (mB/mA)^k exp(-dF/kT)} (Eq. 5): ln u3 < k ln f - dF
     const float kexp = EXACT ? 3.0f : 4.0f;
-    const bool ok = (kexp * lnf - dF) > logf(u3);
+    const bool ok = (kexp * l2f - dF * 1.44269504088896341f) > __builtin_amdgcn_logf(u3);
     ox = ok ? bx : ax;
     oy = ok ? by : ay;
     oz = ok ? bz : az;
@@ -182,19 +182,29 @@ __global__ __launch_bounds__(256) void k_pass4(SweepArgs a, const ClassCoef* __r
         float EL[3], ER[3];
         const bool hy_m = y > 0, hy_p = y + 1 < a.ny, hz_m = z > 0, hz_p = z + 1 < a.nz;
         const bool el = i0 > 0, er = i0 + 4 < a.hw;
-        const int rs = a.hw, ls = a.ny * a.hw;
+        // neighbour rows/slots: load from a clamped (always valid) address, zero what is absent
+        const int dym = hy_m ? -a.hw : 0, dyp = hy_p ? a.hw : 0;
+        const int dzm = hz_m ? -a.ny * a.hw : 0, dzp = hz_p ? a.ny * a.hw : 0;
+        const int del = el ? -1 : 0, der = er ? 4 : 3;
         const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            const float* oc = oth + c * Nc + o0;
             A[c] = *(const float4*)(own + c * Nc + o0);
-            O[c] = *(const float4*)(oth + c * Nc + o0);
-            YM[c] = hy_m ? *(const float4*)(oth + c * Nc + o0 - rs) : zero4;
-            YP[c] = hy_p ? *(const float4*)(oth + c * Nc + o0 + rs) : zero4;
-            ZM[c] = hz_m ? *(const float4*)(oth + c * Nc + o0 - ls) : zero4;
-            ZP[c] = hz_p ? *(const float4*)(oth + c * Nc + o0 + ls) : zero4;
-            EL[c] = el ? oth[c * Nc + o0 - 1] : 0.f;
-            ER[c] = er ? oth[c * Nc + o0 + 4] : 0.f;
+            O[c] = *(const float4*)oc;
+            YM[c] = *(const float4*)(oc + dym);
+            YP[c] = *(const float4*)(oc + dyp);
+            ZM[c] = *(const float4*)(oc + dzm);
+            ZP[c] = *(const float4*)(oc + dzp);
+            EL[c] = oc[del];
+            ER[c] = oc[der];
             if (DMG) H[c] = *(const float4*)(h + (colour * 3 + c) * Nc + o0);
+            if (!hy_m) YM[c] = zero4;
+            if (!hy_p) YP[c] = zero4;
+            if (!hz_m) ZM[c] = zero4;
+            if (!hz_p) ZP[c] = zero4;
+            if (!el) EL[c] = 0.f;
+            if (!er) ER[c] = 0.f;
         }
         auto comp = [](const float4& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w)); };
         float4 OUT[3];
