@@ -37,9 +37,15 @@ template <bool INV> __device__ __forceinline__ float2 twc(float2 a, float c, flo
     return INV ? make_float2(a.x * c - a.y * s, a.x * s + a.y * c) : make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
 }
 
-// LDS index with one slot of skew every 32 (spreads strided writes over banks)
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
-constexpr int lds_len(int n) { return n - 1 + ((n - 1) >> 5) + 1; }
+// LDS index with one slot of skew every 16 float2 (a 16-lane group of 8-byte
+// accesses covers all 32 banks once when its slots differ mod 16); the
+// per-signal stride is kept at 1 mod 16 so the same slot of consecutive
+// signals falls in different banks.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+constexpr int lds_len(int n) {
+    const int l = n - 1 + ((n - 1) >> 4) + 1;
+    return l + ((17 - l % 16) % 16);   // round up to 1 mod 16
+}
 
 template <bool INV> __device__ __forceinline__ void dft2(float2* a) {
     const float2 t = a[0];
@@ -96,24 +102,57 @@ template <int R, bool INV> __device__ __forceinline__ void dft(float2* a) {
     else if constexpr (R == 16) dft16<INV>(a);
 }
 
+// Per-pass twiddle tables (kept in LDS): the pass with sub-size NSUB > 1 and
+// radix RHO uses entry r*NSUB + k = exp(-2 pi i r k / (NSUB*RHO)), r < RHO,
+// k < NSUB, at offset tw_off(N, E, NSUB) of the table.
+constexpr int tw_off(int N, int E, int nsub_target) {
+    int off = 0, ns = 1;
+    while (ns < N && ns != nsub_target) {
+        const int rho = (N / ns) < E ? (N / ns) : E;
+        if (ns > 1) off += ns * rho;
+        ns *= rho;
+    }
+    return off;
+}
+constexpr int tw_len(int N, int E) { return tw_off(N, E, N); }
+
+template <int N, int E>
+__device__ __forceinline__ void build_twiddles(float2* tab, const float2* __restrict__ tw) {
+    int ns = 1, off = 0;
+    while (ns < N) {
+        const int rho = (N / ns) < E ? (N / ns) : E;
+        if (ns > 1) {
+            const int step = TW_N / (ns * rho);
+            for (int idx = threadIdx.x; idx < ns * rho; idx += blockDim.x) {
+                const int r = idx / ns, k = idx - r * ns;
+                tab[off + idx] = tw[r * k * step];
+            }
+            off += ns * rho;
+        }
+        ns *= rho;
+    }
+}
+
 // One Stockham pass, sub-transform size NSUB -> NSUB*RHO, on NS signals
-// v[S0..S0+NS).  Non-final passes write to LDS (signal s at lds + s*ls);
-// the final pass leaves its outputs in registers.
+// v[S0..S0+NS).  Non-final passes write to LDS (signal s at lds + s*ls); the
+// final pass leaves its outputs in registers.  With the skew-16 layout the
+// RHO outputs of a butterfly land at lpad(base) + r*NSUB + (r*NSUB >> 4) for
+// every power-of-two NSUB, so one address per butterfly suffices.
 template <int N, int E, int RHO, int NSUB, bool INV, bool LAST, int NS, int S0, int S>
-__device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* __restrict__ tw, float2* lds, int ls) {
+__device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* tab, float2* lds, int ls) {
     constexpr int T = N / E;
     constexpr int Q = E / RHO;
-    constexpr int STEP = TW_N / (NSUB * RHO);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int b = j + q * T;
         const int k = b & (NSUB - 1);
         float2 w[RHO];
         if constexpr (NSUB > 1) {
+            const float2* twk = tab + tw_off(N, E, NSUB) + k;
 #pragma unroll
-            for (int r = 1; r < RHO; ++r) w[r] = tw[r * k * STEP];
+            for (int r = 1; r < RHO; ++r) w[r] = twk[r * NSUB];
         }
-        const int base = (b - k) * RHO + k;
+        const int wb = lpad((b - k) * RHO + k);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             float2 a[RHO];
@@ -128,35 +167,40 @@ __device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* 
 #pragma unroll
             for (int r = 0; r < RHO; ++r) {
                 if constexpr (LAST) v[S0 + s][q + r * Q] = a[r];
-                else lds[s * ls + lpad(base + r * NSUB)] = a[r];
+                else lds[s * ls + wb + r * NSUB + ((r * NSUB) >> 4)] = a[r];
             }
         }
     }
 }
 
 template <int N, int E, int NSUB, bool INV, int NS, int S0, int S>
-__device__ __forceinline__ void st_passes(float2 (&v)[S][E], int j, const float2* __restrict__ tw, float2* lds, int ls) {
+__device__ __forceinline__ void st_passes(float2 (&v)[S][E], int j, const float2* tab, float2* lds, int ls) {
     if constexpr (NSUB < N) {
         constexpr int T = N / E;
         constexpr int RHO = (N / NSUB) < E ? (N / NSUB) : E;
         constexpr bool LAST = NSUB * RHO >= N;
         if constexpr (!LAST) __syncthreads();   // earlier readers of lds are done
-        st_pass<N, E, RHO, NSUB, INV, LAST, NS, S0, S>(v, j, tw, lds, ls);
+        st_pass<N, E, RHO, NSUB, INV, LAST, NS, S0, S>(v, j, tab, lds, ls);
         if constexpr (!LAST) {
             __syncthreads();
+            const int rb = lpad(j);
 #pragma unroll
             for (int s = 0; s < NS; ++s)
 #pragma unroll
-                for (int m = 0; m < E; ++m) v[S0 + s][m] = lds[s * ls + lpad(j + T * m)];
+                for (int m = 0; m < E; ++m) {
+                    if constexpr (T % 16 == 0) v[S0 + s][m] = lds[s * ls + rb + m * (T + T / 16)];
+                    else v[S0 + s][m] = lds[s * ls + lpad(j + T * m)];
+                }
         }
-        st_passes<N, E, NSUB * RHO, INV, NS, S0, S>(v, j, tw, lds, ls);
+        st_passes<N, E, NSUB * RHO, INV, NS, S0, S>(v, j, tab, lds, ls);
     }
 }
 
-// Full length-N transform (unnormalised) of signals v[S0..S0+NS).
+// Full length-N transform (unnormalised) of signals v[S0..S0+NS); tab holds
+// the per-pass twiddle tables built by build_twiddles<N, E>.
 template <int N, int E, bool INV, int NS, int S0, int S>
-__device__ __forceinline__ void st_fft(float2 (&v)[S][E], int j, const float2* __restrict__ tw, float2* lds, int ls) {
-    st_passes<N, E, 1, INV, NS, S0, S>(v, j, tw, lds, ls);
+__device__ __forceinline__ void st_fft(float2 (&v)[S][E], int j, const float2* tab, float2* lds, int ls) {
+    st_passes<N, E, 1, INV, NS, S0, S>(v, j, tab, lds, ls);
 }
 
 // Blocks are dealt to the 8 XCDs round-robin; renumber them so that
@@ -172,9 +216,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 constexpr int x_E(int L) { return L < 8 ? L : (L / 8 > 256 ? L / 256 : 8); }
 constexpr int x_T(int L) { return L / x_E(L); }
 constexpr int x_rows_conc(int L) { return 256 / x_T(L); }
-constexpr size_t x_lds(int L, int rpt) { return (size_t)x_rows_conc(L) * rpt * lds_len(L) * sizeof(float2); }
-// rows per thread: as many (<= 4) as keep a block's LDS within 72 KB
-constexpr int x_RPT(int L) { return x_lds(L, 4) <= 72 * 1024 ? 4 : (x_lds(L, 2) <= 72 * 1024 ? 2 : 1); }
+constexpr size_t x_lds(int L, int rpt) {
+    return ((size_t)x_rows_conc(L) * rpt * lds_len(L) + tw_len(L, x_E(L))) * sizeof(float2);
+}
+// rows per thread: as many (<= 4) as keep a block's LDS within 80 KB (two blocks per CU)
+constexpr int x_RPT(int L) { return x_lds(L, 4) <= 80 * 1024 ? 4 : (x_lds(L, 2) <= 80 * 1024 ? 2 : 1); }
 constexpr int x_R(int L) { return x_rows_conc(L) * x_RPT(L); }
 
 constexpr int y_E(int nz, int Py) {
@@ -183,7 +229,8 @@ constexpr int y_E(int nz, int Py) {
     while (Py / E > 512) E *= 2;
     return E;
 }
-constexpr int y_NSG(int Py) { return Py <= 2048 ? 3 : 1; }
+// signals per LDS exchange group (divides 3*nz; 6 groups two layers when nz is even)
+constexpr int y_NSG(int nz, int Py) { return (Py <= 2048 && nz % 2 == 0) ? 6 : 3; }
 
 // ---------------------------------------------------------------------
 // x forward: a block holds R consecutive rows of one signal s.
@@ -219,9 +266,11 @@ __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, co
             v[i][q] = t;
         }
     }
-    // row r = rg + RC*i lives at lds + r*LS
+    // row r = rg + RC*i lives at lds + r*LS; twiddle tables after the rows
+    float2* tab = lds + R * LS;
+    build_twiddles<L, E>(tab, tw);
     float2* my = lds + rg * LS;
-    st_fft<L, E, false, RPT, 0, RPT>(v, j, tw, my, RC * LS);
+    st_fft<L, E, false, RPT, 0, RPT>(v, j, tab, my, RC * LS);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
@@ -268,6 +317,8 @@ __global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, co
         }
         lds[r * LS + lpad(k)] = Zv;
     }
+    float2* tab = lds + R * LS;
+    build_twiddles<L, E>(tab, tw);
     __syncthreads();
     float2* my = lds + rg * LS;
     float2 v[RPT][E];
@@ -275,7 +326,7 @@ __global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, co
     for (int i = 0; i < RPT; ++i)
 #pragma unroll
         for (int q = 0; q < E; ++q) v[i][q] = my[i * RC * LS + lpad(j + T * q)];
-    st_fft<L, E, true, RPT, 0, RPT>(v, j, tw, my, RC * LS);
+    st_fft<L, E, true, RPT, 0, RPT>(v, j, tab, my, RC * LS);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int y = y0 + rg + RC * i;
@@ -298,10 +349,10 @@ __global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, co
 
 // Forward or inverse FFT of all S signals in groups of NSG through LDS.
 template <int PY, int E, bool INV, int NSG, int G, int S>
-__device__ __forceinline__ void y_groups(float2 (&v)[S][E], int j, const float2* __restrict__ tw, float2* lds, int ls) {
+__device__ __forceinline__ void y_groups(float2 (&v)[S][E], int j, const float2* __restrict__ twl, float2* lds, int ls) {
     if constexpr (G < S) {
-        st_fft<PY, E, INV, NSG, G, S>(v, j, tw, lds, ls);
-        y_groups<PY, E, INV, NSG, G + NSG, S>(v, j, tw, lds, ls);
+        st_fft<PY, E, INV, NSG, G, S>(v, j, twl, lds, ls);
+        y_groups<PY, E, INV, NSG, G + NSG, S>(v, j, twl, lds, ls);
     }
 }
 
@@ -310,9 +361,11 @@ template <int NZ, int PY>
 __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2* __restrict__ X,
                                                             const float* __restrict__ K,
                                                             const float2* __restrict__ tw) {
-    constexpr int S = 3 * NZ, E = y_E(NZ, PY), T = PY / E, NSG = y_NSG(PY);
+    constexpr int S = 3 * NZ, E = y_E(NZ, PY), T = PY / E, NSG = y_NSG(NZ, PY);
     constexpr int LS = lds_len(PY);
     extern __shared__ float2 lds[];
+    float2* twl = lds + NSG * LS;      // per-pass twiddle tables
+    build_twiddles<PY, E>(twl, tw);
     const int kx = blockIdx.x;
     const int j = threadIdx.x;
     const int ny = a.ny;
@@ -329,7 +382,8 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
             v[s][q] = (q < QH && y < ny) ? src[y] : make_float2(0.f, 0.f);
         }
     }
-    y_groups<PY, E, false, NSG, 0, S>(v, j, tw, lds, LS);
+    __syncthreads();
+    y_groups<PY, E, false, NSG, 0, S>(v, j, twl, lds, LS);
     // direct mixing over layers: H_i(z) = sum_z' sum_j K_ij(z - z') M_j(z')
     constexpr int HP = PY / 2;
 #pragma unroll
@@ -362,7 +416,7 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
 #pragma unroll
         for (int s = 0; s < S; ++s) v[s][q] = H[s];
     }
-    y_groups<PY, E, true, NSG, 0, S>(v, j, tw, lds, LS);
+    y_groups<PY, E, true, NSG, 0, S>(v, j, twl, lds, LS);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         float2* dst = X + ((long long)kx * S + s) * ny;
@@ -379,7 +433,7 @@ template <int NZ, int PY>
 hipError_t launch_ypass_py(const SweepArgs& a, const DemagPlan& p, const float2* tw, hipStream_t s) {
     constexpr int E = y_E(NZ, PY);
     if constexpr (3 * NZ * E <= 96) {
-        constexpr size_t sh = sizeof(float2) * y_NSG(PY) * lds_len(PY);
+        constexpr size_t sh = sizeof(float2) * (y_NSG(NZ, PY) * lds_len(PY) + tw_len(PY, E));
         hipLaunchKernelGGL((k_ypass<NZ, PY>), dim3(p.L + 1), dim3(PY / E), sh, s, a, p.X, (const float*)p.K, tw);
         return hipGetLastError();
     } else {
