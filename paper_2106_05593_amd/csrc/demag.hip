@@ -20,14 +20,18 @@ int ypass_E(int nz, int Py) { return y_E(nz, Py); }
 template <int L>
 static hipError_t launch_x_L(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int mask,
                              const float2* tw, hipStream_t s) {
-    constexpr int R = x_R(L);
-    const int ntiles = (a.ny + R - 1) / R;
-    constexpr size_t sh = x_lds(L, x_RPT(L));
-    if (stage == 0)
-        hipLaunchKernelGGL(k_xfwd<L>, dim3(ntiles * p.S), dim3(256), sh, s, a, p.S, ntiles, m, p.X, tw);
-    else
-        hipLaunchKernelGGL(k_xinv<L>, dim3(ntiles * p.S), dim3(256), sh, s, a, p.S, ntiles, (const float2*)p.X, h,
-                           mask, tw);
+    constexpr int RF = x_RPT(L, 0), RI = x_RPT(L, 2);
+    if (stage == 0) {
+        constexpr int R = x_rows_conc(L) * RF;
+        const int ntiles = (a.ny + R - 1) / R;
+        hipLaunchKernelGGL((k_xfwd<L, RF>), dim3(ntiles * p.S), dim3(256), x_lds(L, RF), s, a, p.S, ntiles, m, p.X,
+                           tw);
+    } else {
+        constexpr int R = x_rows_conc(L) * RI;
+        const int ntiles = (a.ny + R - 1) / R;
+        hipLaunchKernelGGL((k_xinv<L, RI>), dim3(ntiles * p.S), dim3(256), x_lds(L, RI), s, a, p.S, ntiles,
+                           (const float2*)p.X, h, mask, tw);
+    }
     return hipGetLastError();
 }
 

@@ -103,13 +103,13 @@ template <int R, bool INV> __device__ __forceinline__ void dft(float2* a) {
 }
 
 // Per-pass twiddle tables (kept in LDS): the pass with sub-size NSUB > 1 and
-// radix RHO uses entry r*NSUB + k = exp(-2 pi i r k / (NSUB*RHO)), r < RHO,
-// k < NSUB, at offset tw_off(N, E, NSUB) of the table.
+// radix RHO uses entry (r-1)*NSUB + k = exp(-2 pi i r k / (NSUB*RHO)),
+// 1 <= r < RHO, k < NSUB, at offset tw_off(N, E, NSUB) of the table.
 constexpr int tw_off(int N, int E, int nsub_target) {
     int off = 0, ns = 1;
     while (ns < N && ns != nsub_target) {
         const int rho = (N / ns) < E ? (N / ns) : E;
-        if (ns > 1) off += ns * rho;
+        if (ns > 1) off += ns * (rho - 1);
         ns *= rho;
     }
     return off;
@@ -123,11 +123,11 @@ __device__ __forceinline__ void build_twiddles(float2* tab, const float2* __rest
         const int rho = (N / ns) < E ? (N / ns) : E;
         if (ns > 1) {
             const int step = TW_N / (ns * rho);
-            for (int idx = threadIdx.x; idx < ns * rho; idx += blockDim.x) {
-                const int r = idx / ns, k = idx - r * ns;
+            for (int idx = threadIdx.x; idx < ns * (rho - 1); idx += blockDim.x) {
+                const int r = idx / ns + 1, k = idx % ns;
                 tab[off + idx] = tw[r * k * step];
             }
-            off += ns * rho;
+            off += ns * (rho - 1);
         }
         ns *= rho;
     }
@@ -150,7 +150,7 @@ __device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* 
         if constexpr (NSUB > 1) {
             const float2* twk = tab + tw_off(N, E, NSUB) + k;
 #pragma unroll
-            for (int r = 1; r < RHO; ++r) w[r] = twk[r * NSUB];
+            for (int r = 1; r < RHO; ++r) w[r] = twk[(r - 1) * NSUB];
         }
         const int wb = lpad((b - k) * RHO + k);
 #pragma unroll
@@ -219,9 +219,14 @@ constexpr int x_rows_conc(int L) { return 256 / x_T(L); }
 constexpr size_t x_lds(int L, int rpt) {
     return ((size_t)x_rows_conc(L) * rpt * lds_len(L) + tw_len(L, x_E(L))) * sizeof(float2);
 }
-// rows per thread: as many (<= 4) as keep a block's LDS within 80 KB (two blocks per CU)
-constexpr int x_RPT(int L) { return x_lds(L, 4) <= 80 * 1024 ? 4 : (x_lds(L, 2) <= 80 * 1024 ? 2 : 1); }
-constexpr int x_R(int L) { return x_rows_conc(L) * x_RPT(L); }
+// rows per thread: as many (<= 4) as keep a block's LDS within the budget;
+// the inverse (which gathers its input from y-contiguous runs of the
+// spectrum) takes 80 KB (two blocks per CU), the forward 48 KB (more,
+// smaller blocks measured faster there)
+constexpr int x_RPT_lds(int L, int kb) {
+    return x_lds(L, 4) <= kb * 1024 ? 4 : (x_lds(L, 2) <= kb * 1024 ? 2 : 1);
+}
+constexpr int x_RPT(int L, int stage) { return x_RPT_lds(L, stage == 0 ? 48 : 80); }
 
 constexpr int y_E(int nz, int Py) {
     int E = nz <= 4 ? 8 : 4;
@@ -235,10 +240,10 @@ constexpr int y_NSG(int nz, int Py) { return (Py <= 2048 && nz % 2 == 0) ? 6 : 3
 // ---------------------------------------------------------------------
 // x forward: a block holds R consecutive rows of one signal s.
 // ---------------------------------------------------------------------
-template <int L>
+template <int L, int RPT>
 __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, const float* __restrict__ m,
                                               float2* __restrict__ X, const float2* __restrict__ tw) {
-    constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), RPT = x_RPT(L), R = RC * RPT;
+    constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), R = RC * RPT;
     constexpr int LS = lds_len(L);
     extern __shared__ float2 lds[];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -292,10 +297,10 @@ __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, co
 }
 
 // x inverse: mirror of k_xfwd; writes h of colour c when (mask >> c) & 1.
-template <int L>
+template <int L, int RPT>
 __global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, const float2* __restrict__ X,
                                               float* __restrict__ h, int mask, const float2* __restrict__ tw) {
-    constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), RPT = x_RPT(L), R = RC * RPT;
+    constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), R = RC * RPT;
     constexpr int LS = lds_len(L);
     extern __shared__ float2 lds[];
     const int lb = xcd_block(blockIdx.x, gridDim.x);

@@ -163,12 +163,15 @@ __global__ __launch_bounds__(256) void k_pass4(SweepArgs a, const ClassCoef* __r
     const int lb = xcd_block_s(blockIdx.x, gridDim.x);
     const int tflat = lb * 256 + threadIdx.x;
     const int hwc = a.hw >> 2;
-    const int row = tflat / hwc;
-    const int ic = tflat - row * hwc;
+    // rows are taken y-major, z-minor: the nz layers of one y run in adjacent
+    // blocks, so z neighbours are read through the same XCD's L2
+    const int lr = tflat / hwc;
+    const int ic = tflat - lr * hwc;
     double sx = 0, sy = 0, sz = 0, sq = 0;
     unsigned long long nacc = 0;
-    if (row < a.ny * a.nz) {
-        const int z = row / a.ny, y = row - z * a.ny;
+    if (lr < a.ny * a.nz) {
+        const int y = lr / a.nz, z = lr - y * a.nz;
+        const int row = z * a.ny + y;
         const int par = (colour + y + z) & 1;
         const int Nc = (int)a.Nc;
         const int i0 = ic * 4;
@@ -260,12 +263,13 @@ __global__ __launch_bounds__(256) void k_pass1(SweepArgs a, const ClassCoef* __r
                                                SweepAccum* __restrict__ acc, int shift, uint8_t* __restrict__ dec) {
     const int lb = xcd_block_s(blockIdx.x, gridDim.x);
     const int tflat = lb * 256 + threadIdx.x;
-    const int row = tflat / a.hw;
-    const int i = tflat - row * a.hw;
+    const int lr = tflat / a.hw;          // y-major, z-minor row order
+    const int i = tflat - lr * a.hw;
     double sx = 0, sy = 0, sz = 0, sq = 0;
     unsigned long long nacc = 0;
-    if (row < a.ny * a.nz) {
-        const int z = row / a.ny, y = row - z * a.ny;
+    if (lr < a.ny * a.nz) {
+        const int y = lr / a.nz, z = lr - y * a.nz;
+        const int row = z * a.ny + y;
         const int par = (colour + y + z) & 1;
         const int x = 2 * i + par;
         if (x < a.nx) {
