@@ -5,10 +5,14 @@
 //   x forward  rows of nx reals -> Px/2+1 complex bins (Px = padded length) via
 //              a half-length complex FFT of z[n] = x[2n] + i x[2n+1]; with the
 //              colour-split state x[2n] and x[2n+1] are slot n of the two
-//              colour rows.  Output X[(k*S + s)*ny + y], S = 3*nz signals.
-//   y pass     one block per kx: FFT over padded y of all S signals, direct
-//              mixing over layers with the tensor spectrum (all S values of a
-//              bin sit in one thread's registers), inverse FFT, crop.
+//              colour rows.  Output X[(k*S + s)*ny + y], S = 3*nz signals,
+//              k < L; the bins k = 0 and k = L are real and travel packed as
+//              X[0] + i X[L] in row 0.
+//   y pass     one block per kx < L: FFT over padded y of all S signals,
+//              direct mixing over layers with the tensor spectrum (all S
+//              values of a bin sit in one thread's registers), inverse FFT,
+//              crop.  Block 0 splits the packed pair into its two Hermitian
+//              spectra before the mixing and packs the results after it.
 //   x inverse  inverse of the first, writing h of the requested colours.
 //
 // FFT engine: mixed-radix Stockham, length N and E elements per thread fixed
@@ -116,20 +120,33 @@ constexpr int tw_off(int N, int E, int nsub_target) {
 }
 constexpr int tw_len(int N, int E) { return tw_off(N, E, N); }
 
-template <int N, int E>
+// Index into tw[] of table entry idx (passes searched at compile time).
+template <int N, int E, int NS, int OFF>
+__device__ __forceinline__ int tw_src(int idx) {
+    constexpr int RHO = (N / NS) < E ? (N / NS) : E;
+    if constexpr (NS == 1) {
+        return tw_src<N, E, RHO, 0>(idx);
+    } else {
+        constexpr int CNT = NS * (RHO - 1);
+        const int i = idx - OFF;
+        const int src = (i / NS + 1) * (i % NS) * (TW_N / (NS * RHO));
+        if constexpr (NS * RHO >= N) return src;
+        else return idx < OFF + CNT ? src : tw_src<N, E, NS * RHO, OFF + CNT>(idx);
+    }
+}
+
+// Fill the per-pass tables with NT threads; all loads are independent so
+// they are in flight together.
+template <int N, int E, int NT>
 __device__ __forceinline__ void build_twiddles(float2* tab, const float2* __restrict__ tw) {
-    int ns = 1, off = 0;
-    while (ns < N) {
-        const int rho = (N / ns) < E ? (N / ns) : E;
-        if (ns > 1) {
-            const int step = TW_N / (ns * rho);
-            for (int idx = threadIdx.x; idx < ns * (rho - 1); idx += blockDim.x) {
-                const int r = idx / ns + 1, k = idx % ns;
-                tab[off + idx] = tw[r * k * step];
-            }
-            off += ns * (rho - 1);
+    constexpr int LEN = tw_len(N, E);
+    if constexpr (LEN > 0) {
+#pragma unroll
+        for (int i = 0; i < (LEN + NT - 1) / NT; ++i) {
+            // clamped: surplus threads rewrite the last entry with its own value
+            const int idx = min((int)threadIdx.x + NT * i, LEN - 1);
+            tab[idx] = tw[tw_src<N, E, 1, 0>(idx)];
         }
-        ns *= rho;
     }
 }
 
@@ -273,7 +290,7 @@ __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, co
     }
     // row r = rg + RC*i lives at lds + r*LS; twiddle tables after the rows
     float2* tab = lds + R * LS;
-    build_twiddles<L, E>(tab, tw);
+    build_twiddles<L, E, 256>(tab, tw);
     float2* my = lds + rg * LS;
     st_fft<L, E, false, RPT, 0, RPT>(v, j, tab, my, RC * LS);
     __syncthreads();
@@ -284,15 +301,21 @@ __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, co
     __syncthreads();
     // X[k] = A + W^k B, A = (Z[k] + conj Z[L-k])/2, B = (Z[k] - conj Z[L-k])/(2i), W = exp(-i pi/L)
     constexpr int WSTEP = TW_N / (2 * L);
-    for (int e = threadIdx.x; e < R * (L + 1); e += 256) {
+    // (k = 0: X[0] = A + B and X[L] = A - B are real; stored as X[0] + i X[L])
+    // (loop bodies are branch-free apart from the final store, so the
+    // unrolled loads of several iterations are in flight together)
+    static_assert((R * L) % 256 == 0, "x tile covers whole waves");
+#pragma unroll 8
+    for (int i = 0; i < R * L / 256; ++i) {
+        const int e = threadIdx.x + 256 * i;
         const int k = e / R, r = e - k * R, y = y0 + r;
-        if (y >= a.ny) continue;
-        const float2 Zk = lds[r * LS + lpad(k & (L - 1))];
+        const float2 Zk = lds[r * LS + lpad(k)];
         const float2 Zr = lds[r * LS + lpad((L - k) & (L - 1))];
         const float2 A = make_float2(0.5f * (Zk.x + Zr.x), 0.5f * (Zk.y - Zr.y));
         const float2 B = make_float2(0.5f * (Zk.y + Zr.y), -0.5f * (Zk.x - Zr.x));
         const float2 WB = cmul(tw[k * WSTEP], B);
-        X[((long long)k * S + s) * a.ny + y] = make_float2(A.x + WB.x, A.y + WB.y);
+        const float2 out = k == 0 ? make_float2(A.x + B.x, A.x - B.x) : make_float2(A.x + WB.x, A.y + WB.y);
+        if (y < a.ny) X[((long long)k * S + s) * a.ny + y] = out;
     }
 }
 
@@ -309,21 +332,27 @@ __global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, co
     const int j = threadIdx.x % T, rg = threadIdx.x / T;
     constexpr int WSTEP = TW_N / (2 * L);
     // Z[k] = A + i B, A = X[k] + conj X[L-k], B = (X[k] - conj X[L-k]) W^-k
-    for (int e = threadIdx.x; e < R * L; e += 256) {
+    // (row 0 holds the real pair X[0] + i X[L])
+    // (rows past ny read row ny-1 and store zero: no branch around the loads)
+    static_assert((R * L) % 256 == 0, "x tile covers whole waves");
+#pragma unroll 8
+    for (int i = 0; i < R * L / 256; ++i) {
+        const int e = threadIdx.x + 256 * i;
         const int k = e / R, r = e - k * R, y = y0 + r;
-        float2 Zv = make_float2(0.f, 0.f);
-        if (y < a.ny) {
-            const float2 Xa = X[((long long)k * S + s) * a.ny + y];
-            const float2 Xb = X[((long long)(L - k) * S + s) * a.ny + y];
-            const float2 A = make_float2(Xa.x + Xb.x, Xa.y - Xb.y);
-            const float2 D = make_float2(Xa.x - Xb.x, Xa.y + Xb.y);
-            const float2 B = cmulc(D, tw[k * WSTEP]);
-            Zv = make_float2(A.x - B.y, A.y + B.x);
+        const int yc = y < a.ny ? y : a.ny - 1;
+        float2 Xa = X[((long long)k * S + s) * a.ny + yc];
+        float2 Xb = X[((long long)((L - k) & (L - 1)) * S + s) * a.ny + yc];
+        if (k == 0) {
+            Xb = make_float2(Xa.y, 0.f);
+            Xa.y = 0.f;
         }
-        lds[r * LS + lpad(k)] = Zv;
+        const float2 A = make_float2(Xa.x + Xb.x, Xa.y - Xb.y);
+        const float2 D = make_float2(Xa.x - Xb.x, Xa.y + Xb.y);
+        const float2 B = cmulc(D, tw[k * WSTEP]);
+        lds[r * LS + lpad(k)] = y < a.ny ? make_float2(A.x - B.y, A.y + B.x) : make_float2(0.f, 0.f);
     }
     float2* tab = lds + R * LS;
-    build_twiddles<L, E>(tab, tw);
+    build_twiddles<L, E, 256>(tab, tw);
     __syncthreads();
     float2* my = lds + rg * LS;
     float2 v[RPT][E];
@@ -361,7 +390,75 @@ __device__ __forceinline__ void y_groups(float2 (&v)[S][E], int j, const float2*
     }
 }
 
-// y pass: one block per kx, T = PY/E threads; thread j owns bins j + T*q.
+// Block 0 of the y pass carries Z = X0 + i XL, X0 and XL real along y, so
+// their spectra are Hermitian: Y0[k] = (Z[k] + conj Z[-k])/2 and
+// YL[k] = (Z[k] - conj Z[-k])/(2i).  SPLIT keeps Y0[k] in slot k and YL[k]
+// in slot PY-k for 0 < k < PY/2 (slots 0 and PY/2 already hold the real pair
+// (Y0, YL)); the merge maps the mixed (H0, HL) back to W = H0 + i HL over the
+// full range.  Works on the signals in groups of NSG through LDS.
+template <int PY, int E, bool SPLIT, int NSG, int G, int S>
+__device__ __forceinline__ void y_pair(float2 (&v)[S][E], int j, float2* lds, int ls) {
+    if constexpr (G < S) {
+        constexpr int T = PY / E;
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NSG; ++s)
+#pragma unroll
+            for (int q = 0; q < E; ++q) lds[s * ls + lpad(j + T * q)] = v[G + s][q];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NSG; ++s)
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int ky = j + T * q, kp = (PY - ky) & (PY - 1);
+                if (ky == kp) continue;
+                const float2 z = v[G + s][q], p = lds[s * ls + lpad(kp)];
+                if (SPLIT) {
+                    v[G + s][q] = ky < kp ? make_float2(0.5f * (z.x + p.x), 0.5f * (z.y - p.y))
+                                          : make_float2(0.5f * (p.y + z.y), -0.5f * (p.x - z.x));
+                } else {
+                    v[G + s][q] = ky < kp ? make_float2(z.x - p.y, z.y + p.x) : make_float2(p.x + z.y, z.x - p.y);
+                }
+            }
+        y_pair<PY, E, SPLIT, NSG, G + NSG, S>(v, j, lds, ls);
+    }
+}
+
+// Direct mixing of one bin over layers: H_i(z) = sum_z' sum_j K_ij(z - z') M_j(z').
+// Kp: the 6*NZ tensor values of the bin, in registers (xx, yy, zz, xy real; xz, yz
+// imaginary, stored as their imaginary parts), sy = -1 for bins past PY/2.
+template <int NZ>
+__device__ __forceinline__ void load_bin(float (&kv)[6 * NZ], const float* __restrict__ Kp) {
+#pragma unroll
+    for (int i = 0; i < 6 * NZ; ++i) kv[i] = Kp[i];
+}
+template <int NZ>
+__device__ __forceinline__ void mix_layers(const float (&Kp)[6 * NZ], float sy, const float2 (&M)[3 * NZ],
+                                           float2 (&H)[3 * NZ]) {
+#pragma unroll
+    for (int s = 0; s < 3 * NZ; ++s) H[s] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int zo = 0; zo < NZ; ++zo) {
+#pragma unroll
+        for (int zi = 0; zi < NZ; ++zi) {
+            const int dz = zo - zi, adz = dz >= 0 ? dz : -dz;
+            const float sz = dz >= 0 ? 1.0f : -1.0f;
+            const float kxx = Kp[0 * NZ + adz], kyy = Kp[1 * NZ + adz], kzz = Kp[2 * NZ + adz];
+            const float kxy = sy * Kp[3 * NZ + adz], kxz = sz * Kp[4 * NZ + adz], kyz = sy * sz * Kp[5 * NZ + adz];
+            const float2 Mx = M[0 * NZ + zi], My = M[1 * NZ + zi], Mz = M[2 * NZ + zi];
+            // xz, yz spectra are imaginary: (i k) M = (-k M.y, k M.x)
+            H[0 * NZ + zo].x += kxx * Mx.x + kxy * My.x - kxz * Mz.y;
+            H[0 * NZ + zo].y += kxx * Mx.y + kxy * My.y + kxz * Mz.x;
+            H[1 * NZ + zo].x += kxy * Mx.x + kyy * My.x - kyz * Mz.y;
+            H[1 * NZ + zo].y += kxy * Mx.y + kyy * My.y + kyz * Mz.x;
+            H[2 * NZ + zo].x += -kxz * Mx.y - kyz * My.y + kzz * Mz.x;
+            H[2 * NZ + zo].y += kxz * Mx.x + kyz * My.x + kzz * Mz.y;
+        }
+    }
+}
+
+// y pass: one block per kx < L (block 0 also carries kx = L), T = PY/E
+// threads; thread j owns bins j + T*q.
 template <int NZ, int PY>
 __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2* __restrict__ X,
                                                             const float* __restrict__ K,
@@ -370,7 +467,6 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
     constexpr int LS = lds_len(PY);
     extern __shared__ float2 lds[];
     float2* twl = lds + NSG * LS;      // per-pass twiddle tables
-    build_twiddles<PY, E>(twl, tw);
     const int kx = blockIdx.x;
     const int j = threadIdx.x;
     const int ny = a.ny;
@@ -387,39 +483,70 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
             v[s][q] = (q < QH && y < ny) ? src[y] : make_float2(0.f, 0.f);
         }
     }
+    build_twiddles<PY, E, T>(twl, tw);
     __syncthreads();
     y_groups<PY, E, false, NSG, 0, S>(v, j, twl, lds, LS);
-    // direct mixing over layers: H_i(z) = sum_z' sum_j K_ij(z - z') M_j(z')
     constexpr int HP = PY / 2;
+    if (kx != 0) {
+        // the tensor values of bin q+1 are loaded while bin q is mixed
+        auto bin = [&](int q) {
+            const int ky = j + T * q;
+            return K + ((long long)kx * (HP + 1) + (ky <= HP ? ky : PY - ky)) * 6 * NZ;
+        };
+        float kc[6 * NZ];
+        load_bin<NZ>(kc, bin(0));
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int ky = j + T * q;
-        const int kyp = ky <= HP ? ky : PY - ky;
-        const float sy = ky <= HP ? 1.0f : -1.0f;
-        const float* Kp = K + ((long long)kx * (HP + 1) + kyp) * 6 * NZ;
-        float2 H[S];
+        for (int q = 0; q < E; ++q) {
+            float kn[6 * NZ];
+            if (q + 1 < E) load_bin<NZ>(kn, bin(q + 1));
+            const int ky = j + T * q;
+            float2 M[S], H[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) H[s] = make_float2(0.f, 0.f);
+            for (int s = 0; s < S; ++s) M[s] = v[s][q];
+            mix_layers<NZ>(kc, ky <= HP ? 1.0f : -1.0f, M, H);
 #pragma unroll
-        for (int zo = 0; zo < NZ; ++zo) {
+            for (int s = 0; s < S; ++s) v[s][q] = H[s];
+            if (q + 1 < E) {
 #pragma unroll
-            for (int zi = 0; zi < NZ; ++zi) {
-                const int dz = zo - zi, adz = dz >= 0 ? dz : -dz;
-                const float sz = dz >= 0 ? 1.0f : -1.0f;
-                const float kxx = Kp[0 * NZ + adz], kyy = Kp[1 * NZ + adz], kzz = Kp[2 * NZ + adz];
-                const float kxy = sy * Kp[3 * NZ + adz], kxz = sz * Kp[4 * NZ + adz], kyz = sy * sz * Kp[5 * NZ + adz];
-                const float2 Mx = v[0 * NZ + zi][q], My = v[1 * NZ + zi][q], Mz = v[2 * NZ + zi][q];
-                // xz, yz spectra are imaginary: (i k) M = (-k M.y, k M.x)
-                H[0 * NZ + zo].x += kxx * Mx.x + kxy * My.x - kxz * Mz.y;
-                H[0 * NZ + zo].y += kxx * Mx.y + kxy * My.y + kxz * Mz.x;
-                H[1 * NZ + zo].x += kxy * Mx.x + kyy * My.x - kyz * Mz.y;
-                H[1 * NZ + zo].y += kxy * Mx.y + kyy * My.y + kyz * Mz.x;
-                H[2 * NZ + zo].x += -kxz * Mx.y - kyz * My.y + kzz * Mz.x;
-                H[2 * NZ + zo].y += kxz * Mx.x + kyz * My.x + kzz * Mz.y;
+                for (int i = 0; i < 6 * NZ; ++i) kc[i] = kn[i];
             }
         }
+    } else {
+        // kx = 0 in slots k <= PY/2 and kx = L in slots PY-k (both at +k);
+        // the self-paired slots 0 and PY/2 mix the real pair separately
+        y_pair<PY, E, true, NSG, 0, S>(v, j, lds, LS);
+        const float* K0 = K;
+        const float* KL = K + (long long)gridDim.x * (HP + 1) * 6 * NZ;
 #pragma unroll
-        for (int s = 0; s < S; ++s) v[s][q] = H[s];
+        for (int q = 0; q < E; ++q) {
+            const int ky = j + T * q;
+            float2 M[S], H[S];
+            float kv[6 * NZ];
+            if (ky == 0 || ky == HP) {
+                float hx[S];
+                load_bin<NZ>(kv, K0 + (long long)ky * 6 * NZ);
+#pragma unroll
+                for (int s = 0; s < S; ++s) M[s] = make_float2(v[s][q].x, 0.f);
+                mix_layers<NZ>(kv, 1.0f, M, H);
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    hx[s] = H[s].x;
+                    M[s] = make_float2(v[s][q].y, 0.f);
+                }
+                load_bin<NZ>(kv, KL + (long long)ky * 6 * NZ);
+                mix_layers<NZ>(kv, 1.0f, M, H);
+#pragma unroll
+                for (int s = 0; s < S; ++s) v[s][q] = make_float2(hx[s], H[s].x);
+            } else {
+                load_bin<NZ>(kv, ky < HP ? K0 + (long long)ky * 6 * NZ : KL + (long long)(PY - ky) * 6 * NZ);
+#pragma unroll
+                for (int s = 0; s < S; ++s) M[s] = v[s][q];
+                mix_layers<NZ>(kv, 1.0f, M, H);
+#pragma unroll
+                for (int s = 0; s < S; ++s) v[s][q] = H[s];
+            }
+        }
+        y_pair<PY, E, false, NSG, 0, S>(v, j, lds, LS);
     }
     y_groups<PY, E, true, NSG, 0, S>(v, j, twl, lds, LS);
 #pragma unroll
@@ -439,7 +566,7 @@ hipError_t launch_ypass_py(const SweepArgs& a, const DemagPlan& p, const float2*
     constexpr int E = y_E(NZ, PY);
     if constexpr (3 * NZ * E <= 96) {
         constexpr size_t sh = sizeof(float2) * (y_NSG(NZ, PY) * lds_len(PY) + tw_len(PY, E));
-        hipLaunchKernelGGL((k_ypass<NZ, PY>), dim3(p.L + 1), dim3(PY / E), sh, s, a, p.X, (const float*)p.K, tw);
+        hipLaunchKernelGGL((k_ypass<NZ, PY>), dim3(p.L), dim3(PY / E), sh, s, a, p.X, (const float*)p.K, tw);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;   // rejected at context creation
