@@ -245,8 +245,11 @@ constexpr int x_RPT_lds(int L, int kb) {
 }
 constexpr int x_RPT(int L, int stage) { return x_RPT_lds(L, stage == 0 ? 48 : 80); }
 
+// y-pass elements per thread: 4 (two waves per SIMD at 512 threads, which
+// measured faster than 8 elements on 256 threads), more when PY needs it
 constexpr int y_E(int nz, int Py) {
-    int E = nz <= 4 ? 8 : 4;
+    (void)nz;
+    int E = 4;
     if (E > Py) E = Py;
     while (Py / E > 512) E *= 2;
     return E;
@@ -523,20 +526,32 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
             float2 M[S], H[S];
             float kv[6 * NZ];
             if (ky == 0 || ky == HP) {
-                float hx[S];
-                load_bin<NZ>(kv, K0 + (long long)ky * 6 * NZ);
+                // real pair (Y0, YL): the xy, xz and yz spectra vanish on these
+                // four bins (each is odd along x or along y), so the mixing is
+                // the diagonal one, with the kx = 0 tensor on the real part and
+                // the kx = L tensor on the imaginary part
+                const float* k0 = K0 + (long long)ky * 6 * NZ;
+                const float* kl = KL + (long long)ky * 6 * NZ;
 #pragma unroll
-                for (int s = 0; s < S; ++s) M[s] = make_float2(v[s][q].x, 0.f);
-                mix_layers<NZ>(kv, 1.0f, M, H);
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    hx[s] = H[s].x;
-                    M[s] = make_float2(v[s][q].y, 0.f);
+                for (int i = 0; i < 3 * NZ; ++i) {
+                    kv[i] = k0[i];
+                    kv[3 * NZ + i] = kl[i];
                 }
-                load_bin<NZ>(kv, KL + (long long)ky * 6 * NZ);
-                mix_layers<NZ>(kv, 1.0f, M, H);
 #pragma unroll
-                for (int s = 0; s < S; ++s) v[s][q] = make_float2(hx[s], H[s].x);
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int zo = 0; zo < NZ; ++zo) {
+                        float hr = 0.f, hi = 0.f;
+#pragma unroll
+                        for (int zi = 0; zi < NZ; ++zi) {
+                            const int adz = zo >= zi ? zo - zi : zi - zo;
+                            hr += kv[c * NZ + adz] * v[c * NZ + zi][q].x;
+                            hi += kv[3 * NZ + c * NZ + adz] * v[c * NZ + zi][q].y;
+                        }
+                        H[c * NZ + zo] = make_float2(hr, hi);
+                    }
+#pragma unroll
+                for (int s = 0; s < S; ++s) v[s][q] = H[s];
             } else {
                 load_bin<NZ>(kv, ky < HP ? K0 + (long long)ky * 6 * NZ : KL + (long long)(PY - ky) * 6 * NZ);
 #pragma unroll
