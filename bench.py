@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--profile-every", type=int, default=10,
+                    help="bracket every kernel of one timed sweep in this many with HIP events")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -182,7 +184,9 @@ def main():
     torch.cuda.synchronize()
     print("bench: warm-up done, timing %d sweeps" % args.steps, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    ms, cnt = ch.sweep_timed(args.steps)             # synchronises the stream
+    # HIP events around each launch of every profile_every-th sweep (on the
+    # chain's stream); the other sweeps run without instrumentation
+    ms, cnt = ch.sweep_timed(args.steps, every=args.profile_every)   # synchronises the stream
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ch.stats()
@@ -201,7 +205,9 @@ def main():
     ach = per_kernel[dom]["GBs"]
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom), "kernel": dom}
-    sweep_bytes = sum(algorithmic_bytes(grid, True, n) * int(cnt[k]) for k, n in enumerate(KINDS)) / args.steps
+    sampled = (args.steps + args.profile_every - 1) // args.profile_every
+    roofline["event_sampled_sweeps"] = sampled
+    sweep_bytes = sum(algorithmic_bytes(grid, True, n) * int(cnt[k]) for k, n in enumerate(KINDS)) / sampled
     out = {
         "metric": "MC cell-updates/s at 1024x1024x4 w/ demag; batched chains/s vs plain, FP32",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -148,11 +148,14 @@ mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n);
 mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series);
 
 /* Instrumented sweeps: as mmc_sweep, with HIP events recorded on the
- * context's stream before and after every kernel launch; synchronises and
- * returns the summed device time (ms) and the launch count per kernel kind:
+ * context's stream before and after every kernel launch of sweeps
+ * 0, every, 2*every, ... of the n (every >= 1; sampling keeps the event
+ * overhead out of the other sweeps); synchronises and returns the summed
+ * device time (ms) and the launch count per kernel kind over the sampled
+ * sweeps:
  * 0 demag x-forward FFT, 1 demag y-pass (FFT, layer mixing, inverse FFT),
  * 2 demag x-inverse FFT, 3 colour pass, 4 end-of-sweep statistics. */
-mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, double ms_out[5], int32_t launches_out[5]);
+mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[5], int32_t launches_out[5]);
 
 /* Total free energy (J) and its split {exchange, DMI, anisotropy, Zeeman,
  * longitudinal, demag}, with a freshly computed demag field, FP64 sums. */

@@ -146,17 +146,20 @@ struct LaunchProf {
     std::vector<hipEvent_t> ev;
     std::vector<int> kind;
     size_t used = 0;
+    int every = 1;    // instrument sweeps 0, every, 2*every, ...
 };
 
 static mmc_status enqueue_sweeps(mmc_ctx* ctx, int n, double* series, unsigned long long rec_base,
                                  LaunchProf* prof = nullptr) {
+    int sw = 0;
     auto mark = [&](int kind) -> hipError_t {
-        if (!prof) return hipSuccess;
+        if (!prof || sw % prof->every != 0) return hipSuccess;
         if (prof->used + 1 >= prof->ev.size()) return hipErrorInvalidValue;
         if (kind >= 0) prof->kind.push_back(kind);
         return hipEventRecord(prof->ev[prof->used++], ctx->stream);
     };
     for (int s = 0; s < n; ++s) {
+        sw = s;
         for (int c = 0; c < 2; ++c) {
             const bool refresh = ctx->demag && (c == 0 || ctx->run.refresh_per_sweep >= 2);
             if (refresh) {
@@ -430,13 +433,15 @@ mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n) {
     return enqueue_sweeps(ctx, n, nullptr, 0);
 }
 
-mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, double ms_out[5], int32_t launches_out[5]) {
+mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[5], int32_t launches_out[5]) {
     mmc_status s = check_live(ctx);
     if (s != MMC_OK) return s;
-    if (n < 0 || !ms_out || !launches_out) return fail(MMC_ERR_ARG, "bad count or NULL output");
+    if (n < 0 || every < 1 || !ms_out || !launches_out) return fail(MMC_ERR_ARG, "bad count, sampling or NULL output");
     LaunchProf prof;
+    prof.every = every;
     const size_t per_sweep = 2 * (ctx->demag ? 3 : 0) + 3;
-    prof.ev.resize(2 * per_sweep * (size_t)n + 2);
+    const size_t sampled = ((size_t)n + every - 1) / every;
+    prof.ev.resize(2 * per_sweep * sampled + 2);
     mmc_status st = MMC_OK;
     size_t made = 0;
     for (; made < prof.ev.size(); ++made)

@@ -68,7 +68,7 @@ _SIGS = {
     "mmc_get_m": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_sweep": (C.c_int, [C.c_void_p, C.c_int32]),
     "mmc_sweep_record": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
-    "mmc_sweep_timed": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "mmc_sweep_timed": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "mmc_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mmc_demag_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_subsweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -205,12 +205,13 @@ class Chain:
         _check(lib().mmc_sweep_record(self._h, int(n), s.ctypes.data))
         return s
 
-    def sweep_timed(self, n):
-        """n sweeps with per-kernel HIP-event timing: (ms[5], launches[5]) for
-        demag x-forward, demag y-pass, demag x-inverse, colour pass, end of sweep."""
+    def sweep_timed(self, n, every=1):
+        """n sweeps with per-kernel HIP-event timing of sweeps 0, every, ...:
+        (ms[5], launches[5]) summed over the sampled sweeps, for demag
+        x-forward, demag y-pass, demag x-inverse, colour pass, end of sweep."""
         ms = np.zeros(5)
         cnt = np.zeros(5, dtype=np.int32)
-        _check(lib().mmc_sweep_timed(self._h, int(n), ms.ctypes.data, cnt.ctypes.data))
+        _check(lib().mmc_sweep_timed(self._h, int(n), int(every), ms.ctypes.data, cnt.ctypes.data))
         return ms, cnt
 
     def energy(self):

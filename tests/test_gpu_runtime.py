@@ -89,6 +89,25 @@ def test_deterministic_and_record(pkg):
     assert 0 < s[:, 4].max() <= N
 
 
+def test_sweep_timed_sampling(pkg):
+    """Instrumented sweeps run the same kernels (bitwise same state) and count
+    the launches of the sampled sweeps only."""
+    grid = (48, 40, 2)
+    kw = dict(T=550.0, B=(0, 0, 0.2), demag=True, seed=5, init=1, adapt_every=4, **MAT)
+    a = pkg.Chain(grid, (5e-9,) * 3, **kw)
+    b = pkg.Chain(grid, (5e-9,) * 3, **kw)
+    a.sweep(7)
+    ms, cnt = b.sweep_timed(7, every=3)           # sweeps 0, 3, 6 instrumented
+    assert np.array_equal(a.get_m(), b.get_m()) and a.get_state() == b.get_state()
+    assert list(cnt) == [6, 6, 6, 6, 3]
+    assert np.all(ms > 0)
+    ms1, cnt1 = b.sweep_timed(2)
+    assert list(cnt1) == [4, 4, 4, 4, 2]
+    with pytest.raises(pkg.MMCError) as e:
+        b.sweep_timed(2, every=0)
+    assert e.value.status == -1
+
+
 def test_cone_adaptation_on_device(pkg):
     from oracle import oracle as O
     # no coupling, tiny length moves, high T: acceptance ~ 1 -> +1 degree per window
