@@ -39,7 +39,7 @@ def algorithmic_bytes(grid, demag, kind):
     N = nx * ny * nz
     Px, Py = pad_pow2(nx, 2), pad_pow2(ny)
     L, S = Px // 2, 3 * nz
-    spec = (L + 1) * S * ny * 8                     # x-spectrum, complex FP32
+    spec = L * S * ny * 8                           # x-spectrum, complex FP32 (bins 0 and L share row 0)
     tensor = (L + 1) * (Py // 2 + 1) * 6 * nz * 4   # tensor spectrum, FP32
     if kind == "demag_xfwd":
         return 12 * N + spec                        # read m, write spectrum
