@@ -575,11 +575,176 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2*
     }
 }
 
+// ---------------------------------------------------------------------
+// y pass with two thread sets (E = 8, used for even NZ <= 4 and
+// 512 <= PY <= 2048): set g < 2 transforms signals [g*S/2, (g+1)*S/2), so a
+// thread holds half the signals of its 8 bins; for the layer mixing the sets
+// swap half of their bins through LDS, after which each thread holds all S
+// signals of 4 bins, j + T*(i + 4g), i < 4.  Radix-8 passes need three LDS
+// exchanges per transform where radix 4 needs five.
+// ---------------------------------------------------------------------
+constexpr bool y2_use(int nz, int Py) { return nz % 2 == 0 && nz <= 4 && Py >= 512 && Py <= 2048; }
+constexpr int y2_NSG(int nz) { return (3 * nz / 2) % 3 == 0 ? 3 : ((3 * nz / 2) % 2 == 0 ? 2 : 1); }
+
+// Swap bins between the sets: set 0 sends bins 4..7 of its signals and
+// receives the other set's signals at bins 0..3 into the same registers;
+// set 1 sends bins 0..3 and receives bins 4..7.  Signals in groups of NSG.
+template <int T, int NSG, int SH, int G>
+__device__ __forceinline__ void y_swap(float2 (&v)[SH][8], int g, int j, float2* lds) {
+    if constexpr (G < SH) {
+        // (selects rather than branches keep v in registers)
+        const bool g0 = g == 0;
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NSG; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // the empty asm pins both values in registers, so the select is
+                // not folded into a load from a runtime-chosen array element
+                float2 hi = v[G + s][i + 4], lo = v[G + s][i];
+                asm volatile("" : "+v"(hi.x), "+v"(hi.y), "+v"(lo.x), "+v"(lo.y));
+                lds[((g * NSG + s) * 4 + i) * T + j] = g0 ? hi : lo;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NSG; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float2 in = lds[(((1 - g) * NSG + s) * 4 + i) * T + j];
+                v[G + s][i + 4] = g0 ? in : v[G + s][i + 4];
+                v[G + s][i] = g0 ? v[G + s][i] : in;
+            }
+        y_swap<T, NSG, SH, G + NSG>(v, g, j, lds);
+    }
+}
+
+template <int NZ, int PY>
+__global__ __launch_bounds__(PY / 4) void k_ypass2(SweepArgs a, float2* __restrict__ X,
+                                                   const float* __restrict__ K,
+                                                   const float2* __restrict__ tw) {
+    constexpr int S = 3 * NZ, SH = S / 2, E = 8, T = PY / E, NSG = y2_NSG(NZ);
+    constexpr int LS = lds_len(PY), HP = PY / 2, QH = E / 2;
+    extern __shared__ float2 lds[];
+    float2* twl = lds + 2 * NSG * LS;
+    const int kx = blockIdx.x;
+    const int g = threadIdx.x / T, j = threadIdx.x - g * T;
+    const int ny = a.ny;
+    float2 v[SH][E];
+#pragma unroll
+    for (int s = 0; s < SH; ++s) {
+        const float2* src = X + ((long long)kx * S + g * SH + s) * ny;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int y = j + T * q;
+            v[s][q] = (q < QH && y < ny) ? src[y] : make_float2(0.f, 0.f);
+        }
+    }
+    build_twiddles<PY, E, 2 * T>(twl, tw);
+    __syncthreads();
+    float2* mine = lds + g * NSG * LS;
+    y_groups<PY, E, false, NSG, 0, SH>(v, j, twl, mine, LS);
+    if (kx == 0) y_pair<PY, E, true, NSG, 0, SH>(v, j, mine, LS);
+    y_swap<T, NSG, SH, 0>(v, g, j, lds);
+    // signal s' of bin i: s' < SH ? v[s'][i] : v[s' - SH][i + 4]
+    if (kx != 0) {
+        auto bin = [&](int i) {
+            const int ky = j + T * (i + 4 * g);
+            return K + ((long long)kx * (HP + 1) + (ky <= HP ? ky : PY - ky)) * 6 * NZ;
+        };
+        float kc[6 * NZ];
+        load_bin<NZ>(kc, bin(0));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float kn[6 * NZ];
+            if (i + 1 < 4) load_bin<NZ>(kn, bin(i + 1));
+            const int ky = j + T * (i + 4 * g);
+            float2 M[S], H[S];
+#pragma unroll
+            for (int s = 0; s < SH; ++s) {
+                M[s] = v[s][i];
+                M[SH + s] = v[s][i + 4];
+            }
+            mix_layers<NZ>(kc, ky <= HP ? 1.0f : -1.0f, M, H);
+#pragma unroll
+            for (int s = 0; s < SH; ++s) {
+                v[s][i] = H[s];
+                v[s][i + 4] = H[SH + s];
+            }
+            if (i + 1 < 4) {
+#pragma unroll
+                for (int t = 0; t < 6 * NZ; ++t) kc[t] = kn[t];
+            }
+        }
+    } else {
+        // kx = 0 in slots k <= PY/2 and kx = L in slots PY-k (both at +k);
+        // the self-paired slots 0 and PY/2 mix the real pair on the diagonal
+        const float* K0 = K;
+        const float* KL = K + (long long)gridDim.x * (HP + 1) * 6 * NZ;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ky = j + T * (i + 4 * g);
+            float2 M[S], H[S];
+            float kv[6 * NZ];
+#pragma unroll
+            for (int s = 0; s < SH; ++s) {
+                M[s] = v[s][i];
+                M[SH + s] = v[s][i + 4];
+            }
+            if (ky == 0 || ky == HP) {
+                const float* k0 = K0 + (long long)ky * 6 * NZ;
+                const float* kl = KL + (long long)ky * 6 * NZ;
+#pragma unroll
+                for (int t = 0; t < 3 * NZ; ++t) {
+                    kv[t] = k0[t];
+                    kv[3 * NZ + t] = kl[t];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int zo = 0; zo < NZ; ++zo) {
+                        float hr = 0.f, hi = 0.f;
+#pragma unroll
+                        for (int zi = 0; zi < NZ; ++zi) {
+                            const int adz = zo >= zi ? zo - zi : zi - zo;
+                            hr += kv[c * NZ + adz] * M[c * NZ + zi].x;
+                            hi += kv[3 * NZ + c * NZ + adz] * M[c * NZ + zi].y;
+                        }
+                        H[c * NZ + zo] = make_float2(hr, hi);
+                    }
+            } else {
+                load_bin<NZ>(kv, ky < HP ? K0 + (long long)ky * 6 * NZ : KL + (long long)(PY - ky) * 6 * NZ);
+                mix_layers<NZ>(kv, 1.0f, M, H);
+            }
+#pragma unroll
+            for (int s = 0; s < SH; ++s) {
+                v[s][i] = H[s];
+                v[s][i + 4] = H[SH + s];
+            }
+        }
+    }
+    y_swap<T, NSG, SH, 0>(v, g, j, lds);
+    if (kx == 0) y_pair<PY, E, false, NSG, 0, SH>(v, j, mine, LS);
+    y_groups<PY, E, true, NSG, 0, SH>(v, j, twl, mine, LS);
+#pragma unroll
+    for (int s = 0; s < SH; ++s) {
+        float2* dst = X + ((long long)kx * S + g * SH + s) * ny;
+#pragma unroll
+        for (int q = 0; q < QH; ++q) {
+            const int y = j + T * q;
+            if (y < ny) dst[y] = v[s][q];
+        }
+    }
+}
+
 // y-pass launcher for one layer count (instantiated per NZ in its own unit).
 template <int NZ, int PY>
 hipError_t launch_ypass_py(const SweepArgs& a, const DemagPlan& p, const float2* tw, hipStream_t s) {
     constexpr int E = y_E(NZ, PY);
-    if constexpr (3 * NZ * E <= 96) {
+    if constexpr (y2_use(NZ, PY)) {
+        constexpr size_t sh = sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + tw_len(PY, 8));
+        hipLaunchKernelGGL((k_ypass2<NZ, PY>), dim3(p.L), dim3(PY / 4), sh, s, a, p.X, (const float*)p.K, tw);
+        return hipGetLastError();
+    } else if constexpr (3 * NZ * E <= 96) {
         constexpr size_t sh = sizeof(float2) * (y_NSG(NZ, PY) * lds_len(PY) + tw_len(PY, E));
         hipLaunchKernelGGL((k_ypass<NZ, PY>), dim3(p.L), dim3(PY / E), sh, s, a, p.X, (const float*)p.K, tw);
         return hipGetLastError();
