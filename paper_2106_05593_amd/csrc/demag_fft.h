@@ -302,23 +302,33 @@ __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, co
 #pragma unroll
         for (int q = 0; q < E; ++q) my[i * RC * LS + lpad(j + T * q)] = v[i][q];
     __syncthreads();
-    // X[k] = A + W^k B, A = (Z[k] + conj Z[L-k])/2, B = (Z[k] - conj Z[L-k])/(2i), W = exp(-i pi/L)
+    // X[k] = A + W^k B, A = (Z[k] + conj Z[L-k])/2, B = (Z[k] - conj Z[L-k])/(2i), W = exp(-i pi/L).
+    // The pair (k, L-k) shares A and B up to conjugation: X[L-k] = conj(A - W^k B),
+    // so one thread forms both from one pair of LDS reads.  k = 0: X[0] = A + B
+    // and X[L] = A - B are real (stored as X[0] + i X[L]); its partner is the
+    // self-paired bin L/2, X[L/2] = conj Z[L/2].
+    // (loop bodies are branch-free apart from the stores, so the unrolled
+    // reads of several iterations are in flight together)
     constexpr int WSTEP = TW_N / (2 * L);
-    // (k = 0: X[0] = A + B and X[L] = A - B are real; stored as X[0] + i X[L])
-    // (loop bodies are branch-free apart from the final store, so the
-    // unrolled loads of several iterations are in flight together)
-    static_assert((R * L) % 256 == 0, "x tile covers whole waves");
+    constexpr int KH = L >= 2 ? L / 2 : 1;
+    static_assert((R * KH) % 256 == 0, "x tile covers whole waves");
 #pragma unroll 8
-    for (int i = 0; i < R * L / 256; ++i) {
+    for (int i = 0; i < R * KH / 256; ++i) {
         const int e = threadIdx.x + 256 * i;
         const int k = e / R, r = e - k * R, y = y0 + r;
+        const int kb = k == 0 ? KH : L - k;              // partner bin (L/2 for k = 0)
         const float2 Zk = lds[r * LS + lpad(k)];
-        const float2 Zr = lds[r * LS + lpad((L - k) & (L - 1))];
-        const float2 A = make_float2(0.5f * (Zk.x + Zr.x), 0.5f * (Zk.y - Zr.y));
-        const float2 B = make_float2(0.5f * (Zk.y + Zr.y), -0.5f * (Zk.x - Zr.x));
+        const float2 Zr = lds[r * LS + lpad(kb & (L - 1))];
+        const float2 Zo = k == 0 ? Zk : Zr;              // Z[L-k]
+        const float2 A = make_float2(0.5f * (Zk.x + Zo.x), 0.5f * (Zk.y - Zo.y));
+        const float2 B = make_float2(0.5f * (Zk.y + Zo.y), -0.5f * (Zk.x - Zo.x));
         const float2 WB = cmul(tw[k * WSTEP], B);
         const float2 out = k == 0 ? make_float2(A.x + B.x, A.x - B.x) : make_float2(A.x + WB.x, A.y + WB.y);
-        if (y < a.ny) X[((long long)k * S + s) * a.ny + y] = out;
+        const float2 out2 = k == 0 ? make_float2(Zr.x, -Zr.y) : make_float2(A.x - WB.x, WB.y - A.y);
+        if (y < a.ny) {
+            X[((long long)k * S + s) * a.ny + y] = out;
+            if (L >= 2) X[((long long)kb * S + s) * a.ny + y] = out2;
+        }
     }
 }
 
@@ -334,25 +344,30 @@ __global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, co
     const int comp = s / a.nz, z = s - comp * a.nz;
     const int j = threadIdx.x % T, rg = threadIdx.x / T;
     constexpr int WSTEP = TW_N / (2 * L);
-    // Z[k] = A + i B, A = X[k] + conj X[L-k], B = (X[k] - conj X[L-k]) W^-k
-    // (row 0 holds the real pair X[0] + i X[L])
+    // Z[k] = A + i B, A = X[k] + conj X[L-k], B = (X[k] - conj X[L-k]) W^-k; the
+    // partner bin L-k gives Z[L-k] = conj A + i conj B, so one thread forms both
+    // from one pair of loads.  Row 0 holds the real pair P = X[0] + i X[L]:
+    // Z[0] = (P.x + P.y, P.x - P.y); its partner is the self-paired bin L/2,
+    // Z[L/2] = 2 conj X[L/2].
     // (rows past ny read row ny-1 and store zero: no branch around the loads)
-    static_assert((R * L) % 256 == 0, "x tile covers whole waves");
+    constexpr int KH = L >= 2 ? L / 2 : 1;
+    static_assert((R * KH) % 256 == 0, "x tile covers whole waves");
 #pragma unroll 8
-    for (int i = 0; i < R * L / 256; ++i) {
+    for (int i = 0; i < R * KH / 256; ++i) {
         const int e = threadIdx.x + 256 * i;
         const int k = e / R, r = e - k * R, y = y0 + r;
         const int yc = y < a.ny ? y : a.ny - 1;
-        float2 Xa = X[((long long)k * S + s) * a.ny + yc];
-        float2 Xb = X[((long long)((L - k) & (L - 1)) * S + s) * a.ny + yc];
-        if (k == 0) {
-            Xb = make_float2(Xa.y, 0.f);
-            Xa.y = 0.f;
-        }
+        const int kb = k == 0 ? KH : L - k;              // partner bin (L/2 for k = 0)
+        const float2 Xa = X[((long long)k * S + s) * a.ny + yc];
+        const float2 Xb = X[((long long)(kb & (L - 1)) * S + s) * a.ny + yc];
         const float2 A = make_float2(Xa.x + Xb.x, Xa.y - Xb.y);
         const float2 D = make_float2(Xa.x - Xb.x, Xa.y + Xb.y);
         const float2 B = cmulc(D, tw[k * WSTEP]);
-        lds[r * LS + lpad(k)] = y < a.ny ? make_float2(A.x - B.y, A.y + B.x) : make_float2(0.f, 0.f);
+        const float2 z1 = k == 0 ? make_float2(Xa.x + Xa.y, Xa.x - Xa.y) : make_float2(A.x - B.y, A.y + B.x);
+        const float2 z2 = k == 0 ? make_float2(2.f * Xb.x, -2.f * Xb.y) : make_float2(A.x + B.y, B.x - A.y);
+        const bool in = y < a.ny;
+        lds[r * LS + lpad(k)] = in ? z1 : make_float2(0.f, 0.f);
+        if (L >= 2) lds[r * LS + lpad(kb)] = in ? z2 : make_float2(0.f, 0.f);
     }
     float2* tab = lds + R * LS;
     build_twiddles<L, E, 256>(tab, tw);
