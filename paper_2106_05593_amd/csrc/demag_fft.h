@@ -236,14 +236,13 @@ constexpr int x_rows_conc(int L) { return 256 / x_T(L); }
 constexpr size_t x_lds(int L, int rpt) {
     return ((size_t)x_rows_conc(L) * rpt * lds_len(L) + tw_len(L, x_E(L))) * sizeof(float2);
 }
-// rows per thread: as many (<= 4) as keep a block's LDS within the budget;
-// the inverse (which gathers its input from y-contiguous runs of the
-// spectrum) takes 80 KB (two blocks per CU), the forward 48 KB (more,
-// smaller blocks measured faster there)
+// rows per thread: as many (<= 4) as keep a block's LDS within 48 KB (three
+// blocks per CU); at 1024x1024 that is 4 rows per block, which measured
+// faster than 2 or 8 for both directions
 constexpr int x_RPT_lds(int L, int kb) {
     return x_lds(L, 4) <= kb * 1024 ? 4 : (x_lds(L, 2) <= kb * 1024 ? 2 : 1);
 }
-constexpr int x_RPT(int L, int stage) { return x_RPT_lds(L, stage == 0 ? 48 : 80); }
+constexpr int x_RPT(int L, int stage) { return (void)stage, x_RPT_lds(L, 48); }
 
 // y-pass elements per thread: 4 (two waves per SIMD at 512 threads, which
 // measured faster than 8 elements on 256 threads), more when PY needs it
