@@ -189,10 +189,17 @@ mmc_status mmc_get_state(mmc_ctx* ctx, uint64_t* sweep, int32_t* cone_deg, uint6
 mmc_status mmc_set_state(mmc_ctx* ctx, uint64_t sweep, int32_t cone_deg, uint64_t accepts_window);
 
 /* Batches: independent chains (any sizes, temperatures, fields) advanced
- * together.  mmc_batch_sweep enqueues n sweeps of every chain as one HIP graph
- * launch on the first chain's stream; chains stay caller-owned, must outlive
- * the batch and must not be used directly while a batch sweep runs.  All
- * chains must be on the same device.  Results equal running each chain alone. */
+ * together.  Chains of one shape (grid, cell size, grains on/off, demag and
+ * its refresh cadence, move kind, DMI on/off) share every kernel launch, one
+ * chain per grid row of blocks; the shape groups run on streams of their
+ * own.  mmc_batch_sweep enqueues n sweeps of every chain as one HIP graph
+ * launch on the first chain's stream (captured on the first call and again
+ * whenever n or a chain's temperature, field or grains changed); chains stay
+ * caller-owned, must outlive the batch and must not be used directly while a
+ * batch sweep runs.  All chains must be on the same device.  Results equal
+ * running each chain alone, bit for bit.  Errors: MMC_ERR_ARG (NULL, empty,
+ * repeated chain, chains on different devices), MMC_ERR_STATE (a chain had a
+ * device error), MMC_ERR_DEVICE / MMC_ERR_OOM from HIP. */
 mmc_status mmc_batch_create(mmc_ctx* const* chains, int32_t n, mmc_batch** out);
 mmc_status mmc_batch_sweep(mmc_batch* batch, int32_t n);
 mmc_status mmc_batch_sync(mmc_batch* batch);

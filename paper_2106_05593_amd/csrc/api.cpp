@@ -84,9 +84,17 @@ struct mmc_ctx {
     unsigned version = 0;        // bumps when kernel arguments change
 };
 
+// Chains of one shape advance together: one launch per kernel serves all of
+// them (chain = blockIdx.y).  Each group runs on a stream of its own.
+struct BatchGroup {
+    std::vector<int> idx;                 // chains of the group
+    ChainDesc* d_list = nullptr;          // device copies of their descriptors
+};
+
 struct mmc_batch {
     std::vector<mmc_ctx*> ch;
-    std::vector<hipStream_t> streams;
+    std::vector<BatchGroup> groups;
+    std::vector<hipStream_t> streams;     // one per group
     std::vector<hipEvent_t> done;
     hipEvent_t fork = nullptr;
     hipGraph_t graph = nullptr;
@@ -114,6 +122,21 @@ static void update_args(mmc_ctx* c) {
     a.chain = c->run.chain_id;
     c->version++;
 }
+
+// The kernel-side view of one chain.
+static ChainDesc make_desc(const mmc_ctx* ctx) {
+    ChainDesc v{};
+    v.a = ctx->args;
+    v.ctab = ctx->d_ctab;
+    v.cid = ctx->has_classes ? ctx->d_cid : nullptr;
+    v.m = ctx->d_m;
+    v.h = ctx->d_h;
+    v.st = ctx->d_st;
+    v.acc = ctx->d_acc;
+    v.X = ctx->plan.X;
+    return v;
+}
+static Chains single(const mmc_ctx* ctx) { return Chains{make_desc(ctx), nullptr, 1}; }
 
 static mmc_status upload_classes(mmc_ctx* ctx) {
     ctx->ctab.resize(ctx->nclass);
@@ -149,37 +172,45 @@ struct LaunchProf {
     int every = 1;    // instrument sweeps 0, every, 2*every, ...
 };
 
-static mmc_status enqueue_sweeps(mmc_ctx* ctx, int n, double* series, unsigned long long rec_base,
-                                 LaunchProf* prof = nullptr) {
+// n sweeps of the chains ch, all of c0's shape, on stream st.
+static mmc_status enqueue_core(mmc_ctx* c0, const Chains& ch, int n, hipStream_t st, double* series,
+                               unsigned long long rec_base, LaunchProf* prof) {
+    mmc_ctx* ctx = c0;
     int sw = 0;
     auto mark = [&](int kind) -> hipError_t {
         if (!prof || sw % prof->every != 0) return hipSuccess;
         if (prof->used + 1 >= prof->ev.size()) return hipErrorInvalidValue;
         if (kind >= 0) prof->kind.push_back(kind);
-        return hipEventRecord(prof->ev[prof->used++], ctx->stream);
+        return hipEventRecord(prof->ev[prof->used++], st);
     };
+    const bool exact = c0->run.lenmove == MMC_LEN_EXACT, dmi = c0->mat.D0 != 0.0;
     for (int s = 0; s < n; ++s) {
         sw = s;
         for (int c = 0; c < 2; ++c) {
-            const bool refresh = ctx->demag && (c == 0 || ctx->run.refresh_per_sweep >= 2);
+            const bool refresh = c0->demag && (c == 0 || c0->run.refresh_per_sweep >= 2);
             if (refresh) {
-                const int mask = ctx->run.refresh_per_sweep >= 2 ? (1 << c) : 3;
+                const int mask = c0->run.refresh_per_sweep >= 2 ? (1 << c) : 3;
                 for (int stage = 0; stage < 3; ++stage) {
                     HIPCK(mark(-1));
-                    HIPCK(launch_demag_stage(stage, ctx->args, ctx->plan, ctx->d_m, ctx->d_h, mask, ctx->d_tw, ctx->stream));
+                    HIPCK(launch_demag_stage(stage, c0->args, c0->plan, ch, mask, c0->d_tw, st));
                     HIPCK(mark(stage));
                 }
             }
             HIPCK(mark(-1));
-            HIPCK(launch_pass(ctx->args, ctx->has_classes, ctx->demag, ctx->run.lenmove == MMC_LEN_EXACT,
-                              ctx->mat.D0 != 0.0, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, c, ctx->d_st, ctx->d_acc,
-                              ctx->fp_shift, nullptr, ctx->stream));
+            HIPCK(launch_pass(c0->args, c0->has_classes, c0->demag, exact, dmi, ch, c, true, c0->fp_shift, nullptr, st));
             HIPCK(mark(3));
         }
         HIPCK(mark(-1));
-        HIPCK(launch_end_sweep(ctx->d_acc, ctx->fp_shift, ctx->N, ctx->d_st, series, rec_base, ctx->stream));
+        HIPCK(launch_end_sweep(ch, c0->fp_shift, c0->N, series, rec_base, st));
         HIPCK(mark(4));
     }
+    return MMC_OK;
+}
+
+static mmc_status enqueue_sweeps(mmc_ctx* ctx, int n, double* series, unsigned long long rec_base,
+                                 LaunchProf* prof = nullptr) {
+    mmc_status s = enqueue_core(ctx, single(ctx), n, ctx->stream, series, rec_base, prof);
+    if (s != MMC_OK) return s;
     ctx->host_sweep += (unsigned long long)n;
     return MMC_OK;
 }
@@ -488,7 +519,7 @@ mmc_status mmc_demag_field(mmc_ctx* ctx, float* h_out, int on_device) {
     if (s != MMC_OK) return s;
     if (!h_out) return fail(MMC_ERR_ARG, "NULL output");
     if (!ctx->demag) return fail(MMC_ERR_STATE, "demag is off for this context");
-    HIPCK(launch_demag(ctx->args, ctx->plan, ctx->d_m, ctx->d_h, 3, ctx->d_tw, ctx->stream));
+    HIPCK(launch_demag(ctx->args, ctx->plan, single(ctx), 3, ctx->d_tw, ctx->stream));
     float* dst = on_device ? h_out : nullptr;
     if (!on_device) {
         if (!ctx->d_nat) HIPCK(hipMalloc(&ctx->d_nat, sizeof(float) * 3 * (size_t)ctx->N));
@@ -505,7 +536,7 @@ mmc_status mmc_energy(mmc_ctx* ctx, double* E_total, double E_terms[6]) {
     mmc_status s = check_live(ctx);
     if (s != MMC_OK) return s;
     if (!E_total && !E_terms) return fail(MMC_ERR_ARG, "NULL outputs");
-    if (ctx->demag) HIPCK(launch_demag(ctx->args, ctx->plan, ctx->d_m, ctx->d_h, 3, ctx->d_tw, ctx->stream));
+    if (ctx->demag) HIPCK(launch_demag(ctx->args, ctx->plan, single(ctx), 3, ctx->d_tw, ctx->stream));
     const int blocks = (int)std::min<long long>((ctx->N + 255) / 256, 2048);
     if (ctx->epart_n < blocks) {
         if (ctx->d_epart) HIPCK(hipFree(ctx->d_epart));
@@ -538,8 +569,7 @@ mmc_status mmc_subsweep(mmc_ctx* ctx, int32_t colour, const float* h_in, uint8_t
     HIPCK(hipMemsetAsync(acc_out, 255, (size_t)ctx->N, ctx->stream));
     if (h_in) HIPCK(launch_to_split(ctx->args, h_in, ctx->d_h, ctx->stream));
     HIPCK(launch_pass(ctx->args, ctx->has_classes, h_in != nullptr, ctx->run.lenmove == MMC_LEN_EXACT,
-                      ctx->mat.D0 != 0.0, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->d_h, colour, ctx->d_st, nullptr,
-                      ctx->fp_shift, acc_out, ctx->stream));
+                      ctx->mat.D0 != 0.0, single(ctx), colour, false, ctx->fp_shift, acc_out, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
     return MMC_OK;
 }
@@ -597,8 +627,11 @@ mmc_status mmc_sync(mmc_ctx* ctx) {
 }
 
 // ---------------------------------------------------------------------
-// Batches: every chain's sweeps on a stream of its own, forked from and
-// joined back to one stream, captured once as a HIP graph and replayed.
+// Batches: chains are grouped by shape (grid, cell, material classes on/off,
+// demag and its cadence, move kind, DMI on/off); each group advances in
+// shared launches (chain = blockIdx.y) on a stream of its own, the groups
+// forked from and joined back to the first chain's stream.  The sequence is
+// captured once as a HIP graph and replayed.
 // ---------------------------------------------------------------------
 mmc_status mmc_batch_create(mmc_ctx* const* chains, int32_t n, mmc_batch** out) {
     mmc_ctx* ctx = nullptr;
@@ -614,15 +647,6 @@ mmc_status mmc_batch_create(mmc_ctx* const* chains, int32_t n, mmc_batch** out) 
     if (!b) return fail(MMC_ERR_OOM, "host allocation failed");
     b->ch.assign(chains, chains + n);
     HIPCK(hipSetDevice(chains[0]->device));
-    b->streams.resize(n);
-    b->done.resize(n);
-    for (int i = 0; i < n; ++i) {
-        if (hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming) != hipSuccess) {
-            mmc_batch_destroy(b);
-            return fail(MMC_ERR_DEVICE, "stream/event creation failed");
-        }
-    }
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
         mmc_batch_destroy(b);
         return fail(MMC_ERR_DEVICE, "event creation failed");
@@ -639,6 +663,42 @@ static void batch_drop_graph(mmc_batch* b) {
     b->graph_n = -1;
 }
 
+static bool same_shape(const mmc_ctx* a, const mmc_ctx* c) {
+    return a->g.nx == c->g.nx && a->g.ny == c->g.ny && a->g.nz == c->g.nz && a->cs.hx == c->cs.hx &&
+           a->cs.hy == c->cs.hy && a->cs.hz == c->cs.hz && a->has_classes == c->has_classes &&
+           a->demag == c->demag && (!a->demag || a->run.refresh_per_sweep == c->run.refresh_per_sweep) &&
+           a->run.lenmove == c->run.lenmove && (a->mat.D0 != 0.0) == (c->mat.D0 != 0.0);
+}
+
+// Regroups the chains and uploads each group's descriptors.
+static mmc_status batch_regroup(mmc_batch* b) {
+    mmc_ctx* ctx = nullptr;
+    for (auto& g : b->groups)
+        if (g.d_list) HIPCK(hipFree(g.d_list));
+    b->groups.clear();
+    for (int i = 0; i < (int)b->ch.size(); ++i) {
+        bool placed = false;
+        for (auto& g : b->groups)
+            if (same_shape(b->ch[g.idx[0]], b->ch[i])) { g.idx.push_back(i); placed = true; break; }
+        if (!placed) b->groups.push_back(BatchGroup{{i}, nullptr});
+    }
+    for (auto& g : b->groups) {
+        std::vector<ChainDesc> h(g.idx.size());
+        for (size_t k = 0; k < g.idx.size(); ++k) h[k] = make_desc(b->ch[g.idx[k]]);
+        HIPCK(hipMalloc(&g.d_list, sizeof(ChainDesc) * h.size()));
+        HIPCK(hipMemcpy(g.d_list, h.data(), sizeof(ChainDesc) * h.size(), hipMemcpyHostToDevice));
+    }
+    while (b->streams.size() < b->groups.size()) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        HIPCK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        b->streams.push_back(st);
+        HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        b->done.push_back(ev);
+    }
+    return MMC_OK;
+}
+
 mmc_status mmc_batch_sweep(mmc_batch* b, int32_t n) {
     mmc_ctx* ctx = nullptr;
     if (!b) return fail(MMC_ERR_ARG, "NULL batch");
@@ -653,29 +713,26 @@ mmc_status mmc_batch_sweep(mmc_batch* b, int32_t n) {
     if (stale) {
         batch_drop_graph(b);
         // a chain's own stream may hold earlier work: order it before the graph
-        for (size_t i = 1; i < b->ch.size(); ++i) HIPCK(hipStreamSynchronize(b->ch[i]->stream));
+        for (auto* c : b->ch) HIPCK(hipStreamSynchronize(c->stream));
+        mmc_status st = batch_regroup(b);
+        if (st != MMC_OK) return st;
         HIPCK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
         HIPCK(hipEventRecord(b->fork, s0));
-        std::vector<hipStream_t> saved(b->ch.size());
-        mmc_status st = MMC_OK;
-        for (size_t i = 0; i < b->ch.size(); ++i) {
-            mmc_ctx* c = b->ch[i];
-            HIPCK(hipStreamWaitEvent(b->streams[i], b->fork, 0));
-            saved[i] = c->stream;
-            c->stream = b->streams[i];
-            const unsigned long long hs = c->host_sweep;
-            st = enqueue_sweeps(c, n, nullptr, 0);
-            c->host_sweep = hs;
-            c->stream = saved[i];
+        for (size_t gi = 0; gi < b->groups.size() && st == MMC_OK; ++gi) {
+            const BatchGroup& g = b->groups[gi];
+            HIPCK(hipStreamWaitEvent(b->streams[gi], b->fork, 0));
+            const mmc_ctx* c0 = b->ch[g.idx[0]];
+            st = enqueue_core(b->ch[g.idx[0]], Chains{make_desc(c0), g.d_list, (int)g.idx.size()}, n,
+                              b->streams[gi], nullptr, 0, nullptr);
             if (st != MMC_OK) break;
-            HIPCK(hipEventRecord(b->done[i], b->streams[i]));
-            HIPCK(hipStreamWaitEvent(s0, b->done[i], 0));
+            HIPCK(hipEventRecord(b->done[gi], b->streams[gi]));
+            HIPCK(hipStreamWaitEvent(s0, b->done[gi], 0));
         }
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(s0, &g);
-        if (st != MMC_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(s0, &gr);
+        if (st != MMC_OK) { if (gr) (void)hipGraphDestroy(gr); return st; }
         HIPCK(e);
-        b->graph = g;
+        b->graph = gr;
         HIPCK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         b->graph_n = n;
         b->versions.resize(b->ch.size());
@@ -701,6 +758,7 @@ void mmc_batch_destroy(mmc_batch* b) {
         (void)hipStreamSynchronize(b->ch[0]->stream);
     }
     batch_drop_graph(b);
+    for (auto& g : b->groups) if (g.d_list) (void)hipFree(g.d_list);
     for (auto s : b->streams) if (s) (void)hipStreamDestroy(s);
     for (auto e : b->done) if (e) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);

@@ -6,74 +6,83 @@
 namespace mmc {
 
 // y-pass launchers instantiated in ypass.hip (one unit per layer count)
-extern template hipError_t launch_ypass_nz<1>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
-extern template hipError_t launch_ypass_nz<2>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
-extern template hipError_t launch_ypass_nz<3>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
-extern template hipError_t launch_ypass_nz<4>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
-extern template hipError_t launch_ypass_nz<5>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
-extern template hipError_t launch_ypass_nz<6>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
-extern template hipError_t launch_ypass_nz<7>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
-extern template hipError_t launch_ypass_nz<8>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<1>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<2>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<3>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<4>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<5>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<6>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<7>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
+extern template hipError_t launch_ypass_nz<8>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
 
 int ypass_E(int nz, int Py) { return y_E(nz, Py); }
 
 template <int L>
-static hipError_t launch_x_L(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int mask,
+static hipError_t launch_x_L(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int mask,
                              const float2* tw, hipStream_t s) {
     constexpr int RF = x_RPT(L, 0), RI = x_RPT(L, 2);
+    const int gy = c.many ? c.n : 1;
     if (stage == 0) {
         constexpr int R = x_rows_conc(L) * RF;
+        const dim3 grid(((a.ny + R - 1) / R) * p.S, gy);
         const int ntiles = (a.ny + R - 1) / R;
-        hipLaunchKernelGGL((k_xfwd<L, RF>), dim3(ntiles * p.S), dim3(256), x_lds(L, RF), s, a, p.S, ntiles, m, p.X,
-                           tw);
+        if (c.many)
+            hipLaunchKernelGGL((k_xfwd<L, RF, true>), grid, dim3(256), x_lds(L, RF), s, c.one, c.many, p.S, ntiles, tw);
+        else
+            hipLaunchKernelGGL((k_xfwd<L, RF, false>), grid, dim3(256), x_lds(L, RF), s, c.one, c.many, p.S, ntiles, tw);
     } else {
         constexpr int R = x_rows_conc(L) * RI;
+        const dim3 grid(((a.ny + R - 1) / R) * p.S, gy);
         const int ntiles = (a.ny + R - 1) / R;
-        hipLaunchKernelGGL((k_xinv<L, RI>), dim3(ntiles * p.S), dim3(256), x_lds(L, RI), s, a, p.S, ntiles,
-                           (const float2*)p.X, h, mask, tw);
+        if (c.many)
+            hipLaunchKernelGGL((k_xinv<L, RI, true>), grid, dim3(256), x_lds(L, RI), s, c.one, c.many, p.S, ntiles,
+                               mask, tw);
+        else
+            hipLaunchKernelGGL((k_xinv<L, RI, false>), grid, dim3(256), x_lds(L, RI), s, c.one, c.many, p.S, ntiles,
+                               mask, tw);
     }
     return hipGetLastError();
 }
 
-static hipError_t launch_x(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int mask,
+static hipError_t launch_x(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int mask,
                            const float2* tw, hipStream_t s) {
     switch (p.L) {
-        case 1: return launch_x_L<1>(stage, a, p, m, h, mask, tw, s);
-        case 2: return launch_x_L<2>(stage, a, p, m, h, mask, tw, s);
-        case 4: return launch_x_L<4>(stage, a, p, m, h, mask, tw, s);
-        case 8: return launch_x_L<8>(stage, a, p, m, h, mask, tw, s);
-        case 16: return launch_x_L<16>(stage, a, p, m, h, mask, tw, s);
-        case 32: return launch_x_L<32>(stage, a, p, m, h, mask, tw, s);
-        case 64: return launch_x_L<64>(stage, a, p, m, h, mask, tw, s);
-        case 128: return launch_x_L<128>(stage, a, p, m, h, mask, tw, s);
-        case 256: return launch_x_L<256>(stage, a, p, m, h, mask, tw, s);
-        case 512: return launch_x_L<512>(stage, a, p, m, h, mask, tw, s);
-        case 1024: return launch_x_L<1024>(stage, a, p, m, h, mask, tw, s);
-        case 2048: return launch_x_L<2048>(stage, a, p, m, h, mask, tw, s);
+        case 1: return launch_x_L<1>(stage, a, p, c, mask, tw, s);
+        case 2: return launch_x_L<2>(stage, a, p, c, mask, tw, s);
+        case 4: return launch_x_L<4>(stage, a, p, c, mask, tw, s);
+        case 8: return launch_x_L<8>(stage, a, p, c, mask, tw, s);
+        case 16: return launch_x_L<16>(stage, a, p, c, mask, tw, s);
+        case 32: return launch_x_L<32>(stage, a, p, c, mask, tw, s);
+        case 64: return launch_x_L<64>(stage, a, p, c, mask, tw, s);
+        case 128: return launch_x_L<128>(stage, a, p, c, mask, tw, s);
+        case 256: return launch_x_L<256>(stage, a, p, c, mask, tw, s);
+        case 512: return launch_x_L<512>(stage, a, p, c, mask, tw, s);
+        case 1024: return launch_x_L<1024>(stage, a, p, c, mask, tw, s);
+        case 2048: return launch_x_L<2048>(stage, a, p, c, mask, tw, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h,
-                              int colour_mask, const float2* tw, hipStream_t s) {
-    if (stage == 0 || stage == 2) return launch_x(stage, a, p, m, h, colour_mask, tw, s);
+hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask,
+                              const float2* tw, hipStream_t s) {
+    if (stage == 0 || stage == 2) return launch_x(stage, a, p, c, colour_mask, tw, s);
     switch (a.nz) {
-        case 1: return launch_ypass_nz<1>(a, p, tw, s);
-        case 2: return launch_ypass_nz<2>(a, p, tw, s);
-        case 3: return launch_ypass_nz<3>(a, p, tw, s);
-        case 4: return launch_ypass_nz<4>(a, p, tw, s);
-        case 5: return launch_ypass_nz<5>(a, p, tw, s);
-        case 6: return launch_ypass_nz<6>(a, p, tw, s);
-        case 7: return launch_ypass_nz<7>(a, p, tw, s);
-        case 8: return launch_ypass_nz<8>(a, p, tw, s);
+        case 1: return launch_ypass_nz<1>(c, p, tw, s);
+        case 2: return launch_ypass_nz<2>(c, p, tw, s);
+        case 3: return launch_ypass_nz<3>(c, p, tw, s);
+        case 4: return launch_ypass_nz<4>(c, p, tw, s);
+        case 5: return launch_ypass_nz<5>(c, p, tw, s);
+        case 6: return launch_ypass_nz<6>(c, p, tw, s);
+        case 7: return launch_ypass_nz<7>(c, p, tw, s);
+        case 8: return launch_ypass_nz<8>(c, p, tw, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int colour_mask,
-                        const float2* tw, hipStream_t s) {
+hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask, const float2* tw,
+                        hipStream_t s) {
     for (int st = 0; st < 3; ++st) {
-        hipError_t e = launch_demag_stage(st, a, p, m, h, colour_mask, tw, s);
+        hipError_t e = launch_demag_stage(st, a, p, c, colour_mask, tw, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

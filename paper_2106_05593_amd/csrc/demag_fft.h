@@ -259,9 +259,13 @@ constexpr int y_NSG(int nz, int Py) { return (Py <= 2048 && nz % 2 == 0) ? 6 : 3
 // ---------------------------------------------------------------------
 // x forward: a block holds R consecutive rows of one signal s.
 // ---------------------------------------------------------------------
-template <int L, int RPT>
-__global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, const float* __restrict__ m,
-                                              float2* __restrict__ X, const float2* __restrict__ tw) {
+template <int L, int RPT, bool BAT>
+__global__ __launch_bounds__(256) void k_xfwd(ChainDesc d0, const ChainDesc* __restrict__ dl, int S, int ntiles,
+                                              const float2* __restrict__ tw) {
+    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+    const SweepArgs a = cd.a;
+    const float* __restrict__ m = cd.m;
+    float2* __restrict__ X = cd.X;
     constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), R = RC * RPT;
     constexpr int LS = lds_len(L);
     extern __shared__ float2 lds[];
@@ -332,9 +336,13 @@ __global__ __launch_bounds__(256) void k_xfwd(SweepArgs a, int S, int ntiles, co
 }
 
 // x inverse: mirror of k_xfwd; writes h of colour c when (mask >> c) & 1.
-template <int L, int RPT>
-__global__ __launch_bounds__(256) void k_xinv(SweepArgs a, int S, int ntiles, const float2* __restrict__ X,
-                                              float* __restrict__ h, int mask, const float2* __restrict__ tw) {
+template <int L, int RPT, bool BAT>
+__global__ __launch_bounds__(256) void k_xinv(ChainDesc d0, const ChainDesc* __restrict__ dl, int S, int ntiles,
+                                              int mask, const float2* __restrict__ tw) {
+    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+    const SweepArgs a = cd.a;
+    const float2* __restrict__ X = cd.X;
+    float* __restrict__ h = cd.h;
     constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), R = RC * RPT;
     constexpr int LS = lds_len(L);
     extern __shared__ float2 lds[];
@@ -476,10 +484,13 @@ __device__ __forceinline__ void mix_layers(const float (&Kp)[6 * NZ], float sy, 
 
 // y pass: one block per kx < L (block 0 also carries kx = L), T = PY/E
 // threads; thread j owns bins j + T*q.
-template <int NZ, int PY>
-__global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(SweepArgs a, float2* __restrict__ X,
+template <int NZ, int PY, bool BAT>
+__global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const ChainDesc* __restrict__ dl,
                                                             const float* __restrict__ K,
                                                             const float2* __restrict__ tw) {
+    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+    const SweepArgs a = cd.a;
+    float2* __restrict__ X = cd.X;
     constexpr int S = 3 * NZ, E = y_E(NZ, PY), T = PY / E, NSG = y_NSG(NZ, PY);
     constexpr int LS = lds_len(PY);
     extern __shared__ float2 lds[];
@@ -632,10 +643,13 @@ __device__ __forceinline__ void y_swap(float2 (&v)[SH][8], int g, int j, float2*
     }
 }
 
-template <int NZ, int PY>
-__global__ __launch_bounds__(PY / 4) void k_ypass2(SweepArgs a, float2* __restrict__ X,
+template <int NZ, int PY, bool BAT>
+__global__ __launch_bounds__(PY / 4) void k_ypass2(ChainDesc d0, const ChainDesc* __restrict__ dl,
                                                    const float* __restrict__ K,
                                                    const float2* __restrict__ tw) {
+    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+    const SweepArgs a = cd.a;
+    float2* __restrict__ X = cd.X;
     constexpr int S = 3 * NZ, SH = S / 2, E = 8, T = PY / E, NSG = y2_NSG(NZ);
     constexpr int LS = lds_len(PY), HP = PY / 2, QH = E / 2;
     extern __shared__ float2 lds[];
@@ -752,15 +766,25 @@ __global__ __launch_bounds__(PY / 4) void k_ypass2(SweepArgs a, float2* __restri
 
 // y-pass launcher for one layer count (instantiated per NZ in its own unit).
 template <int NZ, int PY>
-hipError_t launch_ypass_py(const SweepArgs& a, const DemagPlan& p, const float2* tw, hipStream_t s) {
+hipError_t launch_ypass_py(const Chains& c, const DemagPlan& p, const float2* tw, hipStream_t s) {
     constexpr int E = y_E(NZ, PY);
     if constexpr (y2_use(NZ, PY)) {
         constexpr size_t sh = sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + tw_len(PY, 8));
-        hipLaunchKernelGGL((k_ypass2<NZ, PY>), dim3(p.L), dim3(PY / 4), sh, s, a, p.X, (const float*)p.K, tw);
+        if (c.many)
+            hipLaunchKernelGGL((k_ypass2<NZ, PY, true>), dim3(p.L, c.n), dim3(PY / 4), sh, s, c.one, c.many,
+                               (const float*)p.K, tw);
+        else
+            hipLaunchKernelGGL((k_ypass2<NZ, PY, false>), dim3(p.L), dim3(PY / 4), sh, s, c.one, c.many,
+                               (const float*)p.K, tw);
         return hipGetLastError();
     } else if constexpr (3 * NZ * E <= 96) {
         constexpr size_t sh = sizeof(float2) * (y_NSG(NZ, PY) * lds_len(PY) + tw_len(PY, E));
-        hipLaunchKernelGGL((k_ypass<NZ, PY>), dim3(p.L), dim3(PY / E), sh, s, a, p.X, (const float*)p.K, tw);
+        if (c.many)
+            hipLaunchKernelGGL((k_ypass<NZ, PY, true>), dim3(p.L, c.n), dim3(PY / E), sh, s, c.one, c.many,
+                               (const float*)p.K, tw);
+        else
+            hipLaunchKernelGGL((k_ypass<NZ, PY, false>), dim3(p.L), dim3(PY / E), sh, s, c.one, c.many,
+                               (const float*)p.K, tw);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;   // rejected at context creation
@@ -768,21 +792,21 @@ hipError_t launch_ypass_py(const SweepArgs& a, const DemagPlan& p, const float2*
 }
 
 template <int NZ>
-hipError_t launch_ypass_nz(const SweepArgs& a, const DemagPlan& p, const float2* tw, hipStream_t s) {
+hipError_t launch_ypass_nz(const Chains& c, const DemagPlan& p, const float2* tw, hipStream_t s) {
     switch (p.Py) {
-        case 1: return launch_ypass_py<NZ, 1>(a, p, tw, s);
-        case 2: return launch_ypass_py<NZ, 2>(a, p, tw, s);
-        case 4: return launch_ypass_py<NZ, 4>(a, p, tw, s);
-        case 8: return launch_ypass_py<NZ, 8>(a, p, tw, s);
-        case 16: return launch_ypass_py<NZ, 16>(a, p, tw, s);
-        case 32: return launch_ypass_py<NZ, 32>(a, p, tw, s);
-        case 64: return launch_ypass_py<NZ, 64>(a, p, tw, s);
-        case 128: return launch_ypass_py<NZ, 128>(a, p, tw, s);
-        case 256: return launch_ypass_py<NZ, 256>(a, p, tw, s);
-        case 512: return launch_ypass_py<NZ, 512>(a, p, tw, s);
-        case 1024: return launch_ypass_py<NZ, 1024>(a, p, tw, s);
-        case 2048: return launch_ypass_py<NZ, 2048>(a, p, tw, s);
-        case 4096: return launch_ypass_py<NZ, 4096>(a, p, tw, s);
+        case 1: return launch_ypass_py<NZ, 1>(c, p, tw, s);
+        case 2: return launch_ypass_py<NZ, 2>(c, p, tw, s);
+        case 4: return launch_ypass_py<NZ, 4>(c, p, tw, s);
+        case 8: return launch_ypass_py<NZ, 8>(c, p, tw, s);
+        case 16: return launch_ypass_py<NZ, 16>(c, p, tw, s);
+        case 32: return launch_ypass_py<NZ, 32>(c, p, tw, s);
+        case 64: return launch_ypass_py<NZ, 64>(c, p, tw, s);
+        case 128: return launch_ypass_py<NZ, 128>(c, p, tw, s);
+        case 256: return launch_ypass_py<NZ, 256>(c, p, tw, s);
+        case 512: return launch_ypass_py<NZ, 512>(c, p, tw, s);
+        case 1024: return launch_ypass_py<NZ, 1024>(c, p, tw, s);
+        case 2048: return launch_ypass_py<NZ, 2048>(c, p, tw, s);
+        case 4096: return launch_ypass_py<NZ, 4096>(c, p, tw, s);
         default: return hipErrorInvalidValue;
     }
 }

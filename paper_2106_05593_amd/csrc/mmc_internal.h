@@ -78,20 +78,52 @@ struct DemagPlan {
     float2* X;        // [(L+1)][S][ny] complex work buffer
     float* K;         // tensor spectrum
 };
+// Everything a sweep-path kernel needs from one chain.  A single chain's is
+// passed by value; for a batch the descriptors of chains of one shape (grid,
+// material classes on/off, demag, move kind) sit in a device array and
+// chain blockIdx.y (blockIdx.x for the end-of-sweep kernel) is served, so
+// the chains advance in shared launches.
+struct ChainDesc {
+    SweepArgs a;
+    const ClassCoef* ctab;
+    const uint32_t* cid;   // per-cell class ids (colour-split) or NULL
+    float* m;              // [2][3][Nc]
+    float* h;              // [2][3][Nc]
+    DevState* st;
+    SweepAccum* acc;
+    float2* X;             // demag work buffer or NULL
+};
+typedef const ChainDesc* DescList;
+
+// The chains a launch serves: one chain passed by value (many == NULL), or
+// n chains whose descriptors sit in a device array.
+struct Chains {
+    ChainDesc one;
+    DescList many;
+    int n;
+};
+template <bool B>
+__device__ __forceinline__ const ChainDesc& chain_at(const ChainDesc& one, const ChainDesc* __restrict__ many,
+                                                     unsigned i) {
+    if constexpr (B) return many[i];
+    else return one;
+}
+
 int ypass_E(int nz, int Py);                    // elements per thread of the y pass
 hipError_t launch_init(const SweepArgs& a, const ClassCoef* ctab, const uint32_t* cid, float* m, int kind,
                        float dx, float dy, float dz, hipStream_t s);
 hipError_t launch_to_split(const SweepArgs& a, const float* nat, float* split, hipStream_t s);
 hipError_t launch_from_split(const SweepArgs& a, const float* split, float* nat, hipStream_t s);
-hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const float* m, float* h,
-                              int colour_mask, const float2* tw, hipStream_t s);
-hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const float* m, float* h, int colour_mask,
-                        const float2* tw, hipStream_t s);
-hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, const ClassCoef* ctab,
-                       const uint32_t* cid, float* m, const float* h, int colour, const DevState* st, SweepAccum* acc,
-                       int shift, uint8_t* dec, hipStream_t s);
-hipError_t launch_end_sweep(SweepAccum* acc, int shift, long long N, DevState* st, double* series,
-                            unsigned long long rec_base, hipStream_t s);
+// Sweep-path launches over the chains c, all of one shape (a: host copy of
+// the shared geometry).
+hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask,
+                              const float2* tw, hipStream_t s);
+hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask, const float2* tw,
+                        hipStream_t s);
+hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, const Chains& c,
+                       int colour, bool stats, int shift, uint8_t* dec, hipStream_t s);
+hipError_t launch_end_sweep(const Chains& c, int shift, long long N, double* series, unsigned long long rec_base,
+                            hipStream_t s);
 int pass_blocks(const SweepArgs& a, bool classes);
 hipError_t launch_energy(const SweepArgs& a, bool classes, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out);

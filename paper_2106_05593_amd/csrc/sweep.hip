@@ -113,9 +113,14 @@ __device__ __forceinline__ void block_stats(double sx, double sy, double sz, dou
 // End of a sweep (one block of kAccBins threads): totals of the bins (exact
 // integer sums), means, accept window, cone adaptation (rate > 0.55: +1
 // degree, < 0.45: -1 degree, kept in [1, 180]), sweep counter; clears the bins.
-__global__ __launch_bounds__(kAccBins) void k_end_sweep(SweepAccum* __restrict__ acc, int shift, long long N,
-                                                        DevState* __restrict__ st, double* __restrict__ series,
+// Block b serves chain b.
+template <bool B>
+__global__ __launch_bounds__(kAccBins) void k_end_sweep(ChainDesc d0, const ChainDesc* __restrict__ dl, int shift,
+                                                        long long N, double* __restrict__ series,
                                                         unsigned long long rec_base) {
+    const ChainDesc& cd = chain_at<B>(d0, dl, blockIdx.x);
+    SweepAccum* __restrict__ acc = cd.acc;
+    DevState* __restrict__ st = cd.st;
     __shared__ long long fin[kAccBins / 64][5];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     long long v[5];
@@ -156,10 +161,16 @@ __global__ __launch_bounds__(kAccBins) void k_end_sweep(SweepAccum* __restrict__
 }
 
 // C = 4: rows hold a multiple of 4 slots (nx % 8 == 0), uniform material.
-template <bool DMG, bool EXACT, bool DMI>
-__global__ __launch_bounds__(256) void k_pass4(SweepArgs a, const ClassCoef* __restrict__ ctab, float* __restrict__ m,
-                                               const float* __restrict__ h, int colour, const DevState* __restrict__ st,
-                                               SweepAccum* __restrict__ acc, int shift, uint8_t* __restrict__ dec) {
+template <bool DMG, bool EXACT, bool DMI, bool B>
+__global__ __launch_bounds__(256) void k_pass4(ChainDesc d0, const ChainDesc* __restrict__ dl, int colour, int stats,
+                                               int shift, uint8_t* __restrict__ dec) {
+    const ChainDesc& cd = chain_at<B>(d0, dl, blockIdx.y);
+    const SweepArgs a = cd.a;
+    const ClassCoef* __restrict__ ctab = cd.ctab;
+    float* __restrict__ m = cd.m;
+    const float* __restrict__ h = cd.h;
+    const DevState* __restrict__ st = cd.st;
+    SweepAccum* __restrict__ acc = stats ? cd.acc : nullptr;
     const int lb = xcd_block_s(blockIdx.x, gridDim.x);
     const int tflat = lb * 256 + threadIdx.x;
     const int hwc = a.hw >> 2;
@@ -256,11 +267,17 @@ __global__ __launch_bounds__(256) void k_pass4(SweepArgs a, const ClassCoef* __r
 }
 
 // C = 1: any grid, optional per-cell material classes (grains).
-template <bool CLS, bool DMG, bool EXACT, bool DMI>
-__global__ __launch_bounds__(256) void k_pass1(SweepArgs a, const ClassCoef* __restrict__ ctab,
-                                               const uint32_t* __restrict__ cid, float* __restrict__ m,
-                                               const float* __restrict__ h, int colour, const DevState* __restrict__ st,
-                                               SweepAccum* __restrict__ acc, int shift, uint8_t* __restrict__ dec) {
+template <bool CLS, bool DMG, bool EXACT, bool DMI, bool B>
+__global__ __launch_bounds__(256) void k_pass1(ChainDesc d0, const ChainDesc* __restrict__ dl, int colour, int stats,
+                                               int shift, uint8_t* __restrict__ dec) {
+    const ChainDesc& cd = chain_at<B>(d0, dl, blockIdx.y);
+    const SweepArgs a = cd.a;
+    const ClassCoef* __restrict__ ctab = cd.ctab;
+    const uint32_t* __restrict__ cid = cd.cid;
+    float* __restrict__ m = cd.m;
+    const float* __restrict__ h = cd.h;
+    const DevState* __restrict__ st = cd.st;
+    SweepAccum* __restrict__ acc = stats ? cd.acc : nullptr;
     const int lb = xcd_block_s(blockIdx.x, gridDim.x);
     const int tflat = lb * 256 + threadIdx.x;
     const int lr = tflat / a.hw;          // y-major, z-minor row order
@@ -326,27 +343,34 @@ int pass_blocks(const SweepArgs& a, bool classes) {
     return (int)((threads + 255) / 256);
 }
 
-template <bool CLS, bool DMG, bool EXACT, bool DMI>
-static void launch_pass_t(const SweepArgs& a, const ClassCoef* ctab, const uint32_t* cid, float* m, const float* h,
-                          int colour, const DevState* st, SweepAccum* acc, int shift, uint8_t* dec, hipStream_t s) {
-    const int nb = pass_blocks(a, CLS);
+template <bool CLS, bool DMG, bool EXACT, bool DMI, bool B>
+static void launch_pass_b(const SweepArgs& a, const Chains& c, int colour, int stats, int shift, uint8_t* dec,
+                          hipStream_t s) {
+    const dim3 grid(pass_blocks(a, CLS), B ? c.n : 1);
     if constexpr (!CLS) {
         if (pass_vec4(a, false)) {
-            hipLaunchKernelGGL((k_pass4<DMG, EXACT, DMI>), dim3(nb), dim3(256), 0, s, a, ctab, m, h, colour, st, acc,
+            hipLaunchKernelGGL((k_pass4<DMG, EXACT, DMI, B>), grid, dim3(256), 0, s, c.one, c.many, colour, stats,
                                shift, dec);
             return;
         }
     }
-    hipLaunchKernelGGL((k_pass1<CLS, DMG, EXACT, DMI>), dim3(nb), dim3(256), 0, s, a, ctab, cid, m, h, colour, st, acc,
-                       shift, dec);
+    hipLaunchKernelGGL((k_pass1<CLS, DMG, EXACT, DMI, B>), grid, dim3(256), 0, s, c.one, c.many, colour, stats, shift,
+                       dec);
 }
 
-hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, const ClassCoef* ctab,
-                       const uint32_t* cid, float* m, const float* h, int colour, const DevState* st, SweepAccum* acc,
-                       int shift, uint8_t* dec, hipStream_t s) {
+template <bool CLS, bool DMG, bool EXACT, bool DMI>
+static void launch_pass_t(const SweepArgs& a, const Chains& c, int colour, int stats, int shift, uint8_t* dec,
+                          hipStream_t s) {
+    if (c.many) launch_pass_b<CLS, DMG, EXACT, DMI, true>(a, c, colour, stats, shift, dec, s);
+    else launch_pass_b<CLS, DMG, EXACT, DMI, false>(a, c, colour, stats, shift, dec, s);
+}
+
+hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, const Chains& c,
+                       int colour, bool stats, int shift, uint8_t* dec, hipStream_t s) {
     const int key = (classes ? 8 : 0) | (demag ? 4 : 0) | (exact ? 2 : 0) | (dmi ? 1 : 0);
+    const int st = stats ? 1 : 0;
 #define MMC_PASS(K, A_, B_, C_, D_) \
-    case K: launch_pass_t<A_, B_, C_, D_>(a, ctab, cid, m, h, colour, st, acc, shift, dec, s); break;
+    case K: launch_pass_t<A_, B_, C_, D_>(a, c, colour, st, shift, dec, s); break;
     switch (key) {
         MMC_PASS(0, false, false, false, false) MMC_PASS(1, false, false, false, true)
         MMC_PASS(2, false, false, true, false)  MMC_PASS(3, false, false, true, true)
@@ -361,9 +385,14 @@ hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact,
     return hipGetLastError();
 }
 
-hipError_t launch_end_sweep(SweepAccum* acc, int shift, long long N, DevState* st, double* series,
-                            unsigned long long rec_base, hipStream_t s) {
-    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(kAccBins), 0, s, acc, shift, N, st, series, rec_base);
+hipError_t launch_end_sweep(const Chains& c, int shift, long long N, double* series, unsigned long long rec_base,
+                            hipStream_t s) {
+    if (c.many)
+        hipLaunchKernelGGL(k_end_sweep<true>, dim3(c.n), dim3(kAccBins), 0, s, c.one, c.many, shift, N, series,
+                           rec_base);
+    else
+        hipLaunchKernelGGL(k_end_sweep<false>, dim3(1), dim3(kAccBins), 0, s, c.one, c.many, shift, N, series,
+                           rec_base);
     return hipGetLastError();
 }
 

@@ -7,5 +7,5 @@
 #endif
 
 namespace mmc {
-template hipError_t launch_ypass_nz<MMC_NZ>(const SweepArgs&, const DemagPlan&, const float2*, hipStream_t);
+template hipError_t launch_ypass_nz<MMC_NZ>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
 }
