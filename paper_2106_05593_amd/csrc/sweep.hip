@@ -161,8 +161,10 @@ __global__ __launch_bounds__(kAccBins) void k_end_sweep(ChainDesc d0, const Chai
 }
 
 // C = 4: rows hold a multiple of 4 slots (nx % 8 == 0), uniform material.
+// (single chain: at most 128 VGPRs for four waves per SIMD, measured faster
+// than three; the batched form needs a few more registers for its chain view)
 template <bool DMG, bool EXACT, bool DMI, bool B>
-__global__ __launch_bounds__(256) void k_pass4(ChainDesc d0, const ChainDesc* __restrict__ dl, int colour, int stats,
+__global__ __launch_bounds__(256, B ? 3 : 4) void k_pass4(ChainDesc d0, const ChainDesc* __restrict__ dl, int colour, int stats,
                                                int shift, uint8_t* __restrict__ dec) {
     const ChainDesc& cd = chain_at<B>(d0, dl, blockIdx.y);
     const SweepArgs a = cd.a;
