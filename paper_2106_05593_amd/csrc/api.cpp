@@ -351,8 +351,10 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
             if (!alloc((void**)&p.X, sizeof(float2) * (size_t)(p.L + 1) * p.S * grid->ny)) break;
             std::vector<float2> tw(8192);
             for (int j = 0; j < 8192; ++j) tw[j] = make_float2((float)std::cos(-2.0 * kPi * j / 8192), (float)std::sin(-2.0 * kPi * j / 8192));
-            if (!alloc((void**)&ctx->d_tw, sizeof(float2) * 8192)) break;
+            if (!alloc((void**)&ctx->d_tw, sizeof(float2) * (8192 + 4096))) break;
             if (hipMemcpy(ctx->d_tw, tw.data(), sizeof(float2) * 8192, hipMemcpyHostToDevice) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "copy"); break; }
+            if (launch_x_twiddles(p, ctx->d_tw, ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "twiddle tables"); break; }
         }
         st = init_state(ctx);
     } while (false);

@@ -79,6 +79,30 @@ hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p,
     }
 }
 
+template <int L>
+static hipError_t launch_xtw_L(float2* tw, hipStream_t s) {
+    hipLaunchKernelGGL(k_x_twiddles<L>, dim3(1), dim3(256), 0, s, tw + TW_N, (const float2*)tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_x_twiddles(const DemagPlan& p, float2* tw, hipStream_t s) {
+    switch (p.L) {
+        case 1: return launch_xtw_L<1>(tw, s);
+        case 2: return launch_xtw_L<2>(tw, s);
+        case 4: return launch_xtw_L<4>(tw, s);
+        case 8: return launch_xtw_L<8>(tw, s);
+        case 16: return launch_xtw_L<16>(tw, s);
+        case 32: return launch_xtw_L<32>(tw, s);
+        case 64: return launch_xtw_L<64>(tw, s);
+        case 128: return launch_xtw_L<128>(tw, s);
+        case 256: return launch_xtw_L<256>(tw, s);
+        case 512: return launch_xtw_L<512>(tw, s);
+        case 1024: return launch_xtw_L<1024>(tw, s);
+        case 2048: return launch_xtw_L<2048>(tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask, const float2* tw,
                         hipStream_t s) {
     for (int st = 0; st < 3; ++st) {

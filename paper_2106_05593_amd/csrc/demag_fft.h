@@ -233,9 +233,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 constexpr int x_E(int L) { return L < 8 ? L : (L / 8 > 256 ? L / 256 : 8); }
 constexpr int x_T(int L) { return L / x_E(L); }
 constexpr int x_rows_conc(int L) { return 256 / x_T(L); }
-constexpr size_t x_lds(int L, int rpt) {
-    return ((size_t)x_rows_conc(L) * rpt * lds_len(L) + tw_len(L, x_E(L))) * sizeof(float2);
-}
+constexpr size_t x_lds(int L, int rpt) { return (size_t)x_rows_conc(L) * rpt * lds_len(L) * sizeof(float2); }
 // rows per thread: as many (<= 4) as keep a block's LDS within 48 KB (three
 // blocks per CU); at 1024x1024 that is 4 rows per block, which measured
 // faster than 2 or 8 for both directions
@@ -294,9 +292,9 @@ __global__ __launch_bounds__(256) void k_xfwd(ChainDesc d0, const ChainDesc* __r
             v[i][q] = t;
         }
     }
-    // row r = rg + RC*i lives at lds + r*LS; twiddle tables after the rows
-    float2* tab = lds + R * LS;
-    build_twiddles<L, E, 256>(tab, tw);
+    // row r = rg + RC*i lives at lds + r*LS; the per-pass twiddle tables
+    // follow the base table in global memory (L1-resident)
+    const float2* tab = tw + TW_N;
     float2* my = lds + rg * LS;
     st_fft<L, E, false, RPT, 0, RPT>(v, j, tab, my, RC * LS);
     __syncthreads();
@@ -333,6 +331,13 @@ __global__ __launch_bounds__(256) void k_xfwd(ChainDesc d0, const ChainDesc* __r
             if (L >= 2) X[((long long)kb * S + s) * a.ny + y] = out2;
         }
     }
+}
+
+// Per-pass twiddle tables of the x transforms (length L, x_E(L) per thread),
+// written once per plan after the base table.
+template <int L>
+__global__ void k_x_twiddles(float2* __restrict__ out, const float2* __restrict__ tw) {
+    build_twiddles<L, x_E(L), 256>(out, tw);
 }
 
 // x inverse: mirror of k_xfwd; writes h of colour c when (mask >> c) & 1.
@@ -376,8 +381,7 @@ __global__ __launch_bounds__(256) void k_xinv(ChainDesc d0, const ChainDesc* __r
         lds[r * LS + lpad(k)] = in ? z1 : make_float2(0.f, 0.f);
         if (L >= 2) lds[r * LS + lpad(kb)] = in ? z2 : make_float2(0.f, 0.f);
     }
-    float2* tab = lds + R * LS;
-    build_twiddles<L, E, 256>(tab, tw);
+    const float2* tab = tw + TW_N;
     __syncthreads();
     float2* my = lds + rg * LS;
     float2 v[RPT][E];

@@ -118,6 +118,9 @@ hipError_t launch_from_split(const SweepArgs& a, const float* split, float* nat,
 // the shared geometry).
 hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask,
                               const float2* tw, hipStream_t s);
+// Fills the x transforms' per-pass twiddle tables at tw + 8192 (tw holds
+// 8192 + 4096 entries, the first 8192 the base table).
+hipError_t launch_x_twiddles(const DemagPlan& p, float2* tw, hipStream_t s);
 hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask, const float2* tw,
                         hipStream_t s);
 hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, const Chains& c,
