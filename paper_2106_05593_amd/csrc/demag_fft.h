@@ -605,21 +605,27 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const 
 }
 
 // ---------------------------------------------------------------------
-// y pass with two thread sets (E = 8, used for even NZ <= 4 and
-// 512 <= PY <= 2048): set g < 2 transforms signals [g*S/2, (g+1)*S/2), so a
-// thread holds half the signals of its 8 bins; for the layer mixing the sets
-// swap half of their bins through LDS, after which each thread holds all S
-// signals of 4 bins, j + T*(i + 4g), i < 4.  Radix-8 passes need three LDS
-// exchanges per transform where radix 4 needs five.
+// y pass with two thread sets (even NZ, E = 8 for NZ <= 4 and 4 above, T =
+// PY/E in [64, 256], 2T <= 512 threads): set g < 2 transforms signals
+// [g*S/2, (g+1)*S/2), so a thread holds half the signals of its E bins; for
+// the layer mixing the sets swap half of their bins through LDS, after which
+// each thread holds all S signals of E/2 bins, j + T*(i + g*E/2), i < E/2.
+// At E = 8 the radix-8 passes need three LDS exchanges per transform where
+// radix 4 needs five.
 // ---------------------------------------------------------------------
-constexpr bool y2_use(int nz, int Py) { return nz % 2 == 0 && nz <= 4 && Py >= 512 && Py <= 2048; }
+constexpr int y2_E(int nz) { return nz <= 4 ? 8 : 4; }
+constexpr bool y2_use(int nz, int Py) {
+    return nz % 2 == 0 && Py / y2_E(nz) >= 64 && Py / y2_E(nz) <= 256;
+}
 constexpr int y2_NSG(int nz) { return (3 * nz / 2) % 3 == 0 ? 3 : ((3 * nz / 2) % 2 == 0 ? 2 : 1); }
 
-// Swap bins between the sets: set 0 sends bins 4..7 of its signals and
-// receives the other set's signals at bins 0..3 into the same registers;
-// set 1 sends bins 0..3 and receives bins 4..7.  Signals in groups of NSG.
-template <int T, int NSG, int SH, int G>
-__device__ __forceinline__ void y_swap(float2 (&v)[SH][8], int g, int j, float2* lds) {
+// Swap bins between the sets (HB = E/2): set 0 sends bins HB..E-1 of its
+// signals and receives the other set's signals at bins 0..HB-1 into the same
+// registers; set 1 sends bins 0..HB-1 and receives bins HB..E-1.  Signals in
+// groups of NSG.
+template <int E, int T, int NSG, int SH, int G>
+__device__ __forceinline__ void y_swap(float2 (&v)[SH][E], int g, int j, float2* lds) {
+    constexpr int HB = E / 2;
     if constexpr (G < SH) {
         // (selects rather than branches keep v in registers)
         const bool g0 = g == 0;
@@ -627,34 +633,34 @@ __device__ __forceinline__ void y_swap(float2 (&v)[SH][8], int g, int j, float2*
 #pragma unroll
         for (int s = 0; s < NSG; ++s)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < HB; ++i) {
                 // the empty asm pins both values in registers, so the select is
                 // not folded into a load from a runtime-chosen array element
-                float2 hi = v[G + s][i + 4], lo = v[G + s][i];
+                float2 hi = v[G + s][i + HB], lo = v[G + s][i];
                 asm volatile("" : "+v"(hi.x), "+v"(hi.y), "+v"(lo.x), "+v"(lo.y));
-                lds[((g * NSG + s) * 4 + i) * T + j] = g0 ? hi : lo;
+                lds[((g * NSG + s) * HB + i) * T + j] = g0 ? hi : lo;
             }
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < NSG; ++s)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float2 in = lds[(((1 - g) * NSG + s) * 4 + i) * T + j];
-                v[G + s][i + 4] = g0 ? in : v[G + s][i + 4];
+            for (int i = 0; i < HB; ++i) {
+                const float2 in = lds[(((1 - g) * NSG + s) * HB + i) * T + j];
+                v[G + s][i + HB] = g0 ? in : v[G + s][i + HB];
                 v[G + s][i] = g0 ? v[G + s][i] : in;
             }
-        y_swap<T, NSG, SH, G + NSG>(v, g, j, lds);
+        y_swap<E, T, NSG, SH, G + NSG>(v, g, j, lds);
     }
 }
 
 template <int NZ, int PY, bool BAT>
-__global__ __launch_bounds__(PY / 4) void k_ypass2(ChainDesc d0, const ChainDesc* __restrict__ dl,
+__global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, const ChainDesc* __restrict__ dl,
                                                    const float* __restrict__ K,
                                                    const float2* __restrict__ tw) {
     const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
     const SweepArgs a = cd.a;
     float2* __restrict__ X = cd.X;
-    constexpr int S = 3 * NZ, SH = S / 2, E = 8, T = PY / E, NSG = y2_NSG(NZ);
+    constexpr int S = 3 * NZ, SH = S / 2, E = y2_E(NZ), HB = E / 2, T = PY / E, NSG = y2_NSG(NZ);
     constexpr int LS = lds_len(PY), HP = PY / 2, QH = E / 2;
     extern __shared__ float2 lds[];
     float2* twl = lds + 2 * NSG * LS;
@@ -676,35 +682,42 @@ __global__ __launch_bounds__(PY / 4) void k_ypass2(ChainDesc d0, const ChainDesc
     float2* mine = lds + g * NSG * LS;
     y_groups<PY, E, false, NSG, 0, SH>(v, j, twl, mine, LS);
     if (kx == 0) y_pair<PY, E, true, NSG, 0, SH>(v, j, mine, LS);
-    y_swap<T, NSG, SH, 0>(v, g, j, lds);
-    // signal s' of bin i: s' < SH ? v[s'][i] : v[s' - SH][i + 4]
+    y_swap<E, T, NSG, SH, 0>(v, g, j, lds);
+    // signal s' of bin i: s' < SH ? v[s'][i] : v[s' - SH][i + HB]
     if (kx != 0) {
         auto bin = [&](int i) {
-            const int ky = j + T * (i + 4 * g);
+            const int ky = j + T * (i + HB * g);
             return K + ((long long)kx * (HP + 1) + (ky <= HP ? ky : PY - ky)) * 6 * NZ;
         };
+        // (for NZ <= 4 the tensor values of bin i+1 are loaded while bin i is
+        // mixed; at larger NZ the registers are not there for it)
+        constexpr bool PF = NZ <= 4;
         float kc[6 * NZ];
         load_bin<NZ>(kc, bin(0));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < HB; ++i) {
             float kn[6 * NZ];
-            if (i + 1 < 4) load_bin<NZ>(kn, bin(i + 1));
-            const int ky = j + T * (i + 4 * g);
+            if (PF && i + 1 < HB) load_bin<NZ>(kn, bin(i + 1));
+            const int ky = j + T * (i + HB * g);
             float2 M[S], H[S];
 #pragma unroll
             for (int s = 0; s < SH; ++s) {
                 M[s] = v[s][i];
-                M[SH + s] = v[s][i + 4];
+                M[SH + s] = v[s][i + HB];
             }
             mix_layers<NZ>(kc, ky <= HP ? 1.0f : -1.0f, M, H);
 #pragma unroll
             for (int s = 0; s < SH; ++s) {
                 v[s][i] = H[s];
-                v[s][i + 4] = H[SH + s];
+                v[s][i + HB] = H[SH + s];
             }
-            if (i + 1 < 4) {
+            if (i + 1 < HB) {
+                if constexpr (PF) {
 #pragma unroll
-                for (int t = 0; t < 6 * NZ; ++t) kc[t] = kn[t];
+                    for (int t = 0; t < 6 * NZ; ++t) kc[t] = kn[t];
+                } else {
+                    load_bin<NZ>(kc, bin(i + 1));
+                }
             }
         }
     } else {
@@ -713,14 +726,14 @@ __global__ __launch_bounds__(PY / 4) void k_ypass2(ChainDesc d0, const ChainDesc
         const float* K0 = K;
         const float* KL = K + (long long)gridDim.x * (HP + 1) * 6 * NZ;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ky = j + T * (i + 4 * g);
+        for (int i = 0; i < HB; ++i) {
+            const int ky = j + T * (i + HB * g);
             float2 M[S], H[S];
             float kv[6 * NZ];
 #pragma unroll
             for (int s = 0; s < SH; ++s) {
                 M[s] = v[s][i];
-                M[SH + s] = v[s][i + 4];
+                M[SH + s] = v[s][i + HB];
             }
             if (ky == 0 || ky == HP) {
                 const float* k0 = K0 + (long long)ky * 6 * NZ;
@@ -750,11 +763,11 @@ __global__ __launch_bounds__(PY / 4) void k_ypass2(ChainDesc d0, const ChainDesc
 #pragma unroll
             for (int s = 0; s < SH; ++s) {
                 v[s][i] = H[s];
-                v[s][i + 4] = H[SH + s];
+                v[s][i + HB] = H[SH + s];
             }
         }
     }
-    y_swap<T, NSG, SH, 0>(v, g, j, lds);
+    y_swap<E, T, NSG, SH, 0>(v, g, j, lds);
     if (kx == 0) y_pair<PY, E, false, NSG, 0, SH>(v, j, mine, LS);
     y_groups<PY, E, true, NSG, 0, SH>(v, j, twl, mine, LS);
 #pragma unroll
@@ -773,12 +786,13 @@ template <int NZ, int PY>
 hipError_t launch_ypass_py(const Chains& c, const DemagPlan& p, const float2* tw, hipStream_t s) {
     constexpr int E = y_E(NZ, PY);
     if constexpr (y2_use(NZ, PY)) {
-        constexpr size_t sh = sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + tw_len(PY, 8));
+        constexpr int E2 = y2_E(NZ);
+        constexpr size_t sh = sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + tw_len(PY, E2));
         if (c.many)
-            hipLaunchKernelGGL((k_ypass2<NZ, PY, true>), dim3(p.L, c.n), dim3(PY / 4), sh, s, c.one, c.many,
+            hipLaunchKernelGGL((k_ypass2<NZ, PY, true>), dim3(p.L, c.n), dim3(2 * PY / E2), sh, s, c.one, c.many,
                                (const float*)p.K, tw);
         else
-            hipLaunchKernelGGL((k_ypass2<NZ, PY, false>), dim3(p.L), dim3(PY / 4), sh, s, c.one, c.many,
+            hipLaunchKernelGGL((k_ypass2<NZ, PY, false>), dim3(p.L), dim3(2 * PY / E2), sh, s, c.one, c.many,
                                (const float*)p.K, tw);
         return hipGetLastError();
     } else if constexpr (3 * NZ * E <= 96) {
