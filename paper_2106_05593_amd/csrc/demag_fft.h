@@ -419,6 +419,27 @@ __device__ __forceinline__ void y_groups(float2 (&v)[S][E], int j, const float2*
     }
 }
 
+// Inverse transforms of signals [G, S) in groups of NSG; after each group,
+// its cropped outputs (bins y = j + T*q < ny, q < QH) go to dst0 + s*ny.
+template <int PY, int E, int NSG, int G, int S, int QH>
+__device__ __forceinline__ void y_inv_store(float2 (&v)[S][E], int j, const float2* __restrict__ twl, float2* lds,
+                                            int ls, float2* __restrict__ dst0, int ny) {
+    if constexpr (G < S) {
+        constexpr int T = PY / E;
+        st_fft<PY, E, true, NSG, G, S>(v, j, twl, lds, ls);
+#pragma unroll
+        for (int s = G; s < G + NSG; ++s) {
+            float2* dst = dst0 + (long long)s * ny;
+#pragma unroll
+            for (int q = 0; q < QH; ++q) {
+                const int y = j + T * q;
+                if (y < ny) dst[y] = v[s][q];
+            }
+        }
+        y_inv_store<PY, E, NSG, G + NSG, S, QH>(v, j, twl, lds, ls, dst0, ny);
+    }
+}
+
 // Block 0 of the y pass carries Z = X0 + i XL, X0 and XL real along y, so
 // their spectra are Hermitian: Y0[k] = (Z[k] + conj Z[-k])/2 and
 // YL[k] = (Z[k] - conj Z[-k])/(2i).  SPLIT keeps Y0[k] in slot k and YL[k]
@@ -769,16 +790,9 @@ __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, cons
     }
     y_swap<E, T, NSG, SH, 0>(v, g, j, lds);
     if (kx == 0) y_pair<PY, E, false, NSG, 0, SH>(v, j, mine, LS);
-    y_groups<PY, E, true, NSG, 0, SH>(v, j, twl, mine, LS);
-#pragma unroll
-    for (int s = 0; s < SH; ++s) {
-        float2* dst = X + ((long long)kx * S + g * SH + s) * ny;
-#pragma unroll
-        for (int q = 0; q < QH; ++q) {
-            const int y = j + T * q;
-            if (y < ny) dst[y] = v[s][q];
-        }
-    }
+    // inverse transforms group by group, each group's outputs stored as soon
+    // as they are final (the stores overlap the next group's transforms)
+    y_inv_store<PY, E, NSG, 0, SH, QH>(v, j, twl, mine, LS, X + ((long long)kx * S + g * SH) * ny, ny);
 }
 
 // y-pass launcher for one layer count (instantiated per NZ in its own unit).
