@@ -1,0 +1,49 @@
+"""Adaptive hysteresis-loop driver (paper Sec. III, hysteresis loops).
+
+At every field step the chain runs chunks of `chunk` sweeps and averages m
+along the field direction over each chunk (from the per-sweep FP64 means the
+library records).  The step is done once at least `min_chunks` chunks have
+run and the last two chunk averages differ by less than `tol` (in units of
+Ms0); the last chunk average is the loop point, and the next field starts from
+the state the chain is in.  As in the paper only the increasing branch is
+simulated; the decreasing branch follows by inverse symmetry,
+m_dec(H) = -m_inc(-H).
+
+The driver is host logic around any object with `set_field(B_tesla[3])` and
+`sweep_record(n) -> (n, 5) array` whose first three columns are <mx>, <my>,
+<mz> after each sweep (`Chain` is one).
+"""
+import numpy as np
+
+
+def field_step(chain, B, direction, chunk=2000, min_chunks=2, tol=0.01, max_chunks=50):
+    """Run one field step; returns (loop point, chunks run, converged)."""
+    if chunk < 1 or min_chunks < 2 or max_chunks < min_chunks or not tol > 0:
+        raise ValueError("need chunk >= 1, 2 <= min_chunks <= max_chunks, tol > 0")
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    chain.set_field(tuple(float(B) * d))
+    prev = None
+    for k in range(1, max_chunks + 1):
+        series = np.asarray(chain.sweep_record(chunk))
+        avg = float(series[:, :3].mean(axis=0) @ d)
+        if k >= min_chunks and abs(avg - prev) < tol:
+            return avg, k, True
+        prev = avg
+    return avg, max_chunks, False
+
+
+def hysteresis_loop(chain, fields, direction=(0.0, 0.0, 1.0), chunk=2000, min_chunks=2, tol=0.01, max_chunks=50):
+    """Increasing-field branch at `fields` (tesla along `direction`, increasing),
+    completed by inverse symmetry.  Returns a dict of arrays: H_inc, m_inc,
+    chunks, converged, and the decreasing branch H_dec, m_dec."""
+    H = np.asarray(fields, dtype=np.float64)
+    if H.ndim != 1 or H.size < 1 or np.any(np.diff(H) <= 0):
+        raise ValueError("fields must be a non-empty increasing sequence")
+    m = np.zeros(H.size)
+    chunks = np.zeros(H.size, dtype=np.int64)
+    conv = np.zeros(H.size, dtype=bool)
+    for i, B in enumerate(H):
+        m[i], chunks[i], conv[i] = field_step(chain, B, direction, chunk, min_chunks, tol, max_chunks)
+    return {"H_inc": H, "m_inc": m, "chunks": chunks, "converged": conv,
+            "H_dec": -H, "m_dec": -m}
