@@ -122,13 +122,16 @@ static double above_tc_m2(double lb, double lbc) {
     return s4 / s2;
 }
 
+/* Temperature of class c (non-uniform temperature profiles, paper Sec. IV). */
+static double T_of(const or_sys* s, int c) { return s->Tcl ? s->Tcl[c] : s->T; }
+
 void or_class_coeffs(const or_sys* s, or_class* out) {
-    double V = s->hx * s->hy * s->hz, kT = OR_KB * s->T;
+    double V = s->hx * s->hy * s->hz;
     for (int c = 0; c < s->nclass; ++c) {
         or_class* o = &out[c];
-        double Tc = s->Tc[c];
-        or_meanfield(s->mf, s->T, Tc, s->mu, &o->me, &o->inv_chi);
-        if (s->T < Tc) {
+        double Tc = s->Tc[c], T = T_of(s, c), kT = OR_KB * T;
+        or_meanfield(s->mf, T, Tc, s->mu, &o->me, &o->inv_chi);
+        if (T < Tc) {
             o->below = 1;
             /* Eq. 7, T < Tc: V Ms0 (m^2 - me^2)^2 / (8 chi me^2 kT) */
             o->la = V * s->Ms0 * o->inv_chi / (8.0 * o->me * o->me * kT);
@@ -144,8 +147,8 @@ void or_class_coeffs(const or_sys* s, or_class* out) {
              * c = 3/10 for the Langevin model (as printed), 1/6 for J=1/2.
              * The quartic coefficient is written in its non-singular form. */
             o->lb = V * s->Ms0 * o->inv_chi / (2.0 * kT);
-            if (s->mf == 0) o->lbc = 9.0 * V * s->Ms0 * Tc / (20.0 * s->mu * s->T);
-            else            o->lbc = V * s->Ms0 * Tc / (12.0 * s->mu * s->T);
+            if (s->mf == 0) o->lbc = 9.0 * V * s->Ms0 * Tc / (20.0 * s->mu * T);
+            else            o->lbc = V * s->Ms0 * Tc / (12.0 * s->mu * T);
             o->sigma = 0.03;
             o->m0 = sqrt(above_tc_m2(o->lb, o->lbc));
         }
@@ -442,8 +445,8 @@ void or_delta_F(const or_sys* s, const or_class* cc, const double* m, const doub
     int nx = s->nx, ny = s->ny, nz = s->nz;
     int64_t N = (int64_t)nx * ny * nz;
     int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
-    double V = s->hx * s->hy * s->hz, kT = OR_KB * s->T;
     int cp = cls_of(s, p);
+    double V = s->hx * s->hy * s->hz, kT = OR_KB * T_of(s, cp);
     const or_class* c = &cc[cp];
     double mA[3] = {m[p], m[N + p], m[2 * N + p]};
     double D[3], S[3];
@@ -502,7 +505,7 @@ void or_delta_F(const or_sys* s, const or_class* cc, const double* m, const doub
 void or_energy(const or_sys* s, const or_class* cc, const double* m, const double* h, double E[6]) {
     int nx = s->nx, ny = s->ny, nz = s->nz;
     int64_t N = (int64_t)nx * ny * nz;
-    double V = s->hx * s->hy * s->hz, kT = OR_KB * s->T;
+    double V = s->hx * s->hy * s->hz;
     for (int k = 0; k < 6; ++k) E[k] = 0.0;
     for (int64_t p = 0; p < N; ++p) {
         int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
@@ -526,7 +529,7 @@ void or_energy(const or_sys* s, const or_class* cc, const double* m, const doubl
         double u = 1.0 - dd * dd;
         E[2] += V * (s->K1[cp] * u + s->K2[cp] * u * u);
         E[3] += -V * s->Ms0 * (mi[0] * s->B[0] + mi[1] * s->B[1] + mi[2] * s->B[2]);
-        E[4] += kT * fl_kT(&cc[cp], mi[0] * mi[0] + mi[1] * mi[1] + mi[2] * mi[2]);
+        E[4] += OR_KB * T_of(s, cp) * fl_kT(&cc[cp], mi[0] * mi[0] + mi[1] * mi[1] + mi[2] * mi[2]);
         if (h) E[5] += -0.5 * OR_MU0 * V * s->Ms0 * s->Ms0 * (mi[0] * h[p] + mi[1] * h[N + p] + mi[2] * h[2 * N + p]);
     }
 }

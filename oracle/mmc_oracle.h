@@ -72,6 +72,10 @@ typedef struct {
     const double* K2;           /* nclass, J/m^3 */
     const double* Tc;           /* nclass, K */
     double bscale;              /* exchange scale across class boundaries */
+    const double* Tcl;          /* nclass temperatures (K) of a non-uniform temperature profile, or NULL:
+                                 * every class at T.  A move at a cell of class c is judged at T_c: every
+                                 * term of its dF is divided by kB*T_c (local detailed balance), and the
+                                 * class's me, chi, sigma and Eq. 7 coefficients are taken at T_c. */
 } or_sys;
 
 /* Fill cls_out[nclass]. */

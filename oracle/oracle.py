@@ -44,7 +44,7 @@ class OrSys(C.Structure):
                 ("seed", C.c_uint64), ("chain_id", C.c_uint32), ("sigma_fixed", C.c_double),
                 ("nclass", C.c_int32), ("cls", C.POINTER(C.c_uint32)), ("ea", C.POINTER(C.c_double)),
                 ("K1", C.POINTER(C.c_double)), ("K2", C.POINTER(C.c_double)), ("Tc", C.POINTER(C.c_double)),
-                ("bscale", C.c_double)]
+                ("bscale", C.c_double), ("Tcl", C.POINTER(C.c_double))]
 
 
 _dp = C.POINTER(C.c_double)
@@ -156,7 +156,7 @@ class System:
 
     def __init__(self, grid, cell, Ms0, A0, K1, Tc, T, D0=0.0, K2=0.0, easy_axis=(0, 0, 1), B=(0, 0, 0),
                  mf=1, mu=MUB, lenmode=0, demag=False, refresh_per_sweep=2, seed=0, chain_id=0,
-                 sigma_fixed=0.0, cls=None, ea=None, K1s=None, K2s=None, Tcs=None, bscale=1.0):
+                 sigma_fixed=0.0, cls=None, ea=None, K1s=None, K2s=None, Tcs=None, bscale=1.0, Tcl=None):
         self.grid = tuple(int(v) for v in grid)
         self.cell = tuple(float(v) for v in cell)
         self.N = int(np.prod(self.grid))
@@ -187,6 +187,11 @@ class System:
         s.cls = _ptr(self._cls, C.c_uint32) if self._cls is not None else C.POINTER(C.c_uint32)()
         s.ea, s.K1, s.K2, s.Tc = _ptr(self._ea), _ptr(self._K1), _ptr(self._K2), _ptr(self._Tc)
         s.bscale = float(bscale)
+        # per-class temperatures (non-uniform temperature profile), or None: all at T
+        self._Tcl = None if Tcl is None else np.ascontiguousarray(Tcl, dtype=np.float64)
+        if self._Tcl is not None:
+            assert self._Tcl.shape == (self.nclass,)
+        s.Tcl = _ptr(self._Tcl) if self._Tcl is not None else C.POINTER(C.c_double)()
         self.s = s
         self.refresh()
         self._plan = None

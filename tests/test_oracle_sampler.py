@@ -147,3 +147,39 @@ def test_deterministic(oracle_mod):
     S.run(a, 20, cone_deg=30, adapt_every=5)
     S.run(b, 20, cone_deg=30, adapt_every=5)
     assert np.array_equal(a, b)
+
+
+def test_uniform_class_temperatures_change_nothing(oracle_mod):
+    """Per-class temperatures all equal to T reproduce the uniform chain bit for bit."""
+    kw = dict(Ms0=1e6, A0=1e-11, K1=5e4, Tc=700.0, T=450.0, B=(0, 0, 0.1), D0=1e-3, seed=3)
+    cls = (np.arange(12 * 10) % 3).astype(np.uint32)
+    grains = dict(cls=cls, ea=np.tile([0.0, 0.0, 1.0], (3, 1)), K1s=np.full(3, 5e4), Tcs=np.full(3, 700.0))
+    a = oracle_mod.System((12, 10, 1), (5e-9,) * 3, **grains, **kw)
+    b = oracle_mod.System((12, 10, 1), (5e-9,) * 3, Tcl=np.full(3, 450.0), **grains, **kw)
+    ma, mb = a.init_state("random"), b.init_state("random")
+    sa, _, _ = a.run(ma, 6, cone_deg=40)
+    sb, _, _ = b.run(mb, 6, cone_deg=40)
+    assert np.array_equal(ma, mb) and np.array_equal(sa, sb)
+
+
+def test_macrospins_at_their_own_temperatures(oracle_mod):
+    """Non-uniform temperature profile (paper Sec. IV): independent cells of
+    two classes at 0.6 Tc and 1.05 Tc each sample Eq. 1 at their own T
+    (exact length mode), against the single-temperature quadrature."""
+    Tc, Bz, K1 = 700.0, 0.1, 5e4
+    temps = np.array([0.6 * Tc, 1.05 * Tc])
+    N = 64 * 64
+    cls = (np.arange(N) % 2).astype(np.uint32)
+    S = oracle_mod.System((64, 64, 1), (5e-9,) * 3, Ms0=1e6, A0=0.0, K1=K1, Tc=Tc, T=temps[0], B=(0, 0, Bz),
+                          lenmode=1, sigma_fixed=0.25, seed=21, cls=cls, ea=np.tile([0.0, 0.0, 1.0], (2, 1)),
+                          K1s=np.full(2, K1), Tcs=np.full(2, Tc), Tcl=temps)
+    m = S.init_state("uniform")
+    snaps = snapshots(S, m, 80, 1500, 10)
+    for c, T in enumerate(temps):
+        ref = oracle_mod.System((4, 4, 1), (5e-9,) * 3, Ms0=1e6, A0=0.0, K1=K1, Tc=Tc, T=T, B=(0, 0, Bz))
+        mz_q, m2_q = quadrature(ref, K1, Bz)
+        sel = snaps[:, :, cls == c]
+        mz, se_mz = batch_se(sel[:, 2, :].mean(axis=1))
+        m2, se_m2 = batch_se((sel ** 2).sum(axis=1).mean(axis=1))
+        assert abs(mz - mz_q) < 4 * se_mz + 2e-3, (T, mz, mz_q, se_mz)
+        assert abs(m2 - m2_q) < 4 * se_m2 + 2e-3, (T, m2, m2_q, se_m2)
