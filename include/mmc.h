@@ -133,8 +133,21 @@ mmc_status mmc_set_grains(mmc_ctx* ctx, const uint32_t* grain_of_cell, uint32_t 
                           const double* Tc, double boundary_exchange_scale);
 
 mmc_status mmc_set_field(mmc_ctx* ctx, const double mu0H_tesla[3]);
-/* Re-solves me(T), chi_par(T), sigma; the state is kept. */
+/* Re-solves me(T), chi_par(T), sigma; the state is kept.  Clears per-grain
+ * temperatures (every grain at T). */
 mmc_status mmc_set_temperature(mmc_ctx* ctx, double T_kelvin);
+
+/* Non-uniform temperature profile (paper Sec. IV, laser-heated films): grain
+ * k (as set by mmc_set_grains; bin the cells of a profile into grains of
+ * equal temperature) is held at T_of_grain[k] kelvin (host array, n_grains =
+ * the grain count, each > 0 and finite); NULL returns every grain to the
+ * chain temperature.  A move at a cell of grain k is judged at T_k: every term
+ * of its free-energy change is divided by kB*T_k, and the grain's me, chi_par,
+ * sigma and Eq. 7 coefficients are taken at T_k.  The state is kept; a later
+ * mmc_set_temperature or mmc_set_grains clears the profile.  Errors:
+ * MMC_ERR_STATE without grains, MMC_ERR_ARG for a count mismatch,
+ * MMC_ERR_DOMAIN for a non-positive or non-finite temperature. */
+mmc_status mmc_set_grain_temperatures(mmc_ctx* ctx, const double* T_of_grain, uint32_t n_grains);
 
 /* State in/out, natural SoA layout (3*N floats).  set: every |m_i| > 0 and
  * finite, else MMC_ERR_DOMAIN.  get synchronises the stream. */

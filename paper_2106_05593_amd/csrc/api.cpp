@@ -60,6 +60,7 @@ struct mmc_ctx {
     int nclass = 1;
     bool has_classes = false;
     std::vector<double> ea, K1, K2, Tc;
+    std::vector<double> Tg;      // per-grain temperatures (empty: every grain at run.T)
     double bscale = 1.0;
     std::vector<ClassCoef> ctab;
     ClassCoef* d_ctab = nullptr;
@@ -141,7 +142,8 @@ static Chains single(const mmc_ctx* ctx) { return Chains{make_desc(ctx), nullptr
 static mmc_status upload_classes(mmc_ctx* ctx) {
     ctx->ctab.resize(ctx->nclass);
     for (int k = 0; k < ctx->nclass; ++k)
-        ctx->ctab[k] = class_coef(ctx->mat, ctx->run.T, ctx->V, ctx->K1[k], ctx->K2[k], &ctx->ea[3 * k], ctx->Tc[k],
+        ctx->ctab[k] = class_coef(ctx->mat, ctx->Tg.empty() ? ctx->run.T : ctx->Tg[k], ctx->run.T, ctx->V,
+                                  ctx->K1[k], ctx->K2[k], &ctx->ea[3 * k], ctx->Tc[k],
                                   ctx->run.sigma_fixed, 1);
     if (ctx->d_ctab) { HIPCK(hipFree(ctx->d_ctab)); ctx->d_ctab = nullptr; }
     HIPCK(hipMalloc(&ctx->d_ctab, sizeof(ClassCoef) * ctx->nclass));
@@ -390,6 +392,7 @@ mmc_status mmc_set_grains(mmc_ctx* ctx, const uint32_t* grain_of_cell, uint32_t 
     ctx->K1.assign(K1, K1 + n_grains); ctx->K2.assign(K2, K2 + n_grains); ctx->Tc.assign(Tc, Tc + n_grains);
     ctx->bscale = boundary_exchange_scale;
     ctx->has_classes = true;
+    ctx->Tg.clear();
     if (!ctx->d_cid) HIPCK(hipMalloc(&ctx->d_cid, sizeof(uint32_t) * 2 * (size_t)ctx->Nc));
     HIPCK(hipMemcpy(ctx->d_cid, split.data(), sizeof(uint32_t) * split.size(), hipMemcpyHostToDevice));
     update_args(ctx);
@@ -415,6 +418,24 @@ mmc_status mmc_set_temperature(mmc_ctx* ctx, double T) {
     if (!(T > 0) || !std::isfinite(T)) return fail(MMC_ERR_DOMAIN, "temperature must be > 0");
     HIPCK(hipStreamSynchronize(ctx->stream));
     ctx->run.T = T;
+    ctx->Tg.clear();
+    update_args(ctx);
+    return upload_classes(ctx);
+}
+
+mmc_status mmc_set_grain_temperatures(mmc_ctx* ctx, const double* T_of_grain, uint32_t n_grains) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!ctx->has_classes) return fail(MMC_ERR_STATE, "no grains: call mmc_set_grains first");
+    if (T_of_grain) {
+        if ((int)n_grains != ctx->nclass) return fail(MMC_ERR_ARG, "%u temperatures for %d grains", n_grains, ctx->nclass);
+        for (uint32_t k = 0; k < n_grains; ++k)
+            if (!(T_of_grain[k] > 0) || !std::isfinite(T_of_grain[k]))
+                return fail(MMC_ERR_DOMAIN, "grain %u: temperature must be > 0", k);
+    }
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    if (T_of_grain) ctx->Tg.assign(T_of_grain, T_of_grain + n_grains);
+    else ctx->Tg.clear();
     update_args(ctx);
     return upload_classes(ctx);
 }

@@ -100,11 +100,13 @@ __global__ __launch_bounds__(256) void k_energy(SweepArgs a, const ClassCoef* __
         }
         const double dd = (double)mx * C.ex + (double)my * C.ey + (double)mz * C.ez;
         const double u = 1.0 - dd * dd;
-        e[2] += (double)C.ka1 * u + (double)C.ka2 * u * u;
+        // (class terms are in units of the class's kT: 1/tsc converts to the chain's kT0)
+        const double cs = CLS ? 1.0 / (double)C.tsc : 1.0;
+        e[2] += cs * ((double)C.ka1 * u + (double)C.ka2 * u * u);
         e[3] += -((double)a.bx * mx + (double)a.by * my + (double)a.bz * mz);
         const double q = (double)mx * mx + (double)my * my + (double)mz * mz;
-        if (C.below != 0.0f) { const double dq = q - C.me2; e[4] += (double)C.la * dq * dq; }
-        else e[4] += (double)C.lb * q + (double)C.lbc * q * q;
+        if (C.below != 0.0f) { const double dq = q - C.me2; e[4] += cs * (double)C.la * dq * dq; }
+        else e[4] += cs * ((double)C.lb * q + (double)C.lbc * q * q);
         if (h) {
             const long long ih = ((long long)c * 3) * a.Nc + idx;
             e[5] += -0.5 * (double)a.cdm * ((double)mx * h[ih] + (double)my * h[ih + a.Nc] + (double)mz * h[ih + 2 * a.Nc]);

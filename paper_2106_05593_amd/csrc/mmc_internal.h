@@ -23,7 +23,8 @@ struct alignas(16) ClassCoef {
     float m0;        // initial length
     float ex, ey, ez;  // easy axis (unit)
     float ka1, ka2;  // V K1/kT, V K2/kT
-    float pad;
+    float tsc;       // T0/T of the class: factor on the terms the chain keeps in units of kT0
+                     // (exchange, DMI, Zeeman, demag); 1 at a uniform temperature
 };
 static_assert(sizeof(ClassCoef) == 64, "ClassCoef layout");
 
@@ -62,7 +63,8 @@ struct SweepAccum {
 
 // Host-side physics setup (setup.cpp).
 void meanfield(int model, double T, double Tc, double mu, double* me, double* inv_chi);
-ClassCoef class_coef(const mmc_material& mat, double T, double V, double K1, double K2, const double* ea,
+// T: the class's temperature; T0: the chain's reference temperature (kT0 units of SweepArgs).
+ClassCoef class_coef(const mmc_material& mat, double T, double T0, double V, double K1, double K2, const double* ea,
                      double Tc, double sigma_fixed, int nthreads);
 // Demag tensor spectrum K[kx][ky'][q][dz] (kx in [0, Px/2], ky' in [0, Py/2],
 // q = xx,yy,zz,xy,xz,yz, dz in [0,nz)), including the -1/(Px Py) factor.

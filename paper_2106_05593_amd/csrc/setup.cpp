@@ -83,7 +83,7 @@ static double mean_m2_above(double lb, double lbc) {
     return s4 / s2;
 }
 
-ClassCoef class_coef(const mmc_material& mat, double T, double V, double K1, double K2, const double* ea,
+ClassCoef class_coef(const mmc_material& mat, double T, double T0, double V, double K1, double K2, const double* ea,
                      double Tc, double sigma_fixed, int /*nthreads*/) {
     ClassCoef c{};
     double me = 0.0, ic = 0.0;
@@ -116,6 +116,7 @@ ClassCoef class_coef(const mmc_material& mat, double T, double V, double K1, dou
     c.ex = (float)(ea[0] / en); c.ey = (float)(ea[1] / en); c.ez = (float)(ea[2] / en);
     c.ka1 = (float)(V * K1 / kT);
     c.ka2 = (float)(V * K2 / kT);
+    c.tsc = (float)(T0 / T);
     return c;
 }
 

@@ -23,7 +23,10 @@ struct Nbr {          // one neighbour: value and exchange weight (0 when absent
 };
 
 // Proposal and acceptance of one cell.  Returns the decision, writes the new m.
-template <bool EXACT, bool DMI, bool DMG>
+// TS: per-class temperatures; the exchange, DMI, Zeeman and demag terms are
+// formed in units of the chain's kT0 and scaled by C.tsc = T0/T of the class,
+// so every term of dF is in units of the cell's own kT (local detailed balance).
+template <bool EXACT, bool DMI, bool DMG, bool TS>
 __device__ __forceinline__ bool cell_move(const SweepArgs& a, const ClassCoef& C, const uint4 r, const float omc,
                                           const float ax, const float ay, const float az, const Nbr (&nb)[6],
                                           const float hx, const float hy, const float hz,
@@ -56,14 +59,15 @@ __device__ __forceinline__ bool cell_move(const SweepArgs& a, const ClassCoef& C
     const float bx = Lb * nbx, by = Lb * nby, bz = Lb * nbz;
     const float Dx = bx - ax, Dy = by - ay, Dz = bz - az;
     const float Sx = bx + ax, Sy = by + ay, Sz = bz + az;
-    // 3) free-energy change / kT
-    float dF = 0.0f;
+    // 3) free-energy change / kT (with TS: the chain terms accumulate in dFc)
+    float dF = 0.0f, dFc = 0.0f;
+    float& dch = TS ? dFc : dF;
 #pragma unroll
     for (int k = 0; k < 6; ++k)   // exchange: exact change of sum_bonds w |m_i - m_j|^2
-        dF += nb[k].w * (Dx * (Sx - 2.0f * nb[k].x) + Dy * (Sy - 2.0f * nb[k].y) + Dz * (Sz - 2.0f * nb[k].z));
+        dch += nb[k].w * (Dx * (Sx - 2.0f * nb[k].x) + Dy * (Sy - 2.0f * nb[k].y) + Dz * (Sz - 2.0f * nb[k].z));
     if (DMI)   // interfacial DMI (Eq. 15), central differences
-        dF -= a.cdx * (Dz * (nb[1].x - nb[0].x) - Dx * (nb[1].z - nb[0].z)) +
-              a.cdy * (Dz * (nb[3].y - nb[2].y) - Dy * (nb[3].z - nb[2].z));
+        dch -= a.cdx * (Dz * (nb[1].x - nb[0].x) - Dx * (nb[1].z - nb[0].z)) +
+               a.cdy * (Dz * (nb[3].y - nb[2].y) - Dy * (nb[3].z - nb[2].z));
     {   // uniaxial anisotropy (Eq. 11)
         const float dA = ax * C.ex + ay * C.ey + az * C.ez;
         const float dB = bx * C.ex + by * C.ey + bz * C.ez;
@@ -71,13 +75,14 @@ __device__ __forceinline__ bool cell_move(const SweepArgs& a, const ClassCoef& C
         const float pAmB = -dd * (dA + dB);
         dF += pAmB * (C.ka1 + C.ka2 * (2.0f - (dA * dA + dB * dB)));
     }
-    dF -= a.bx * Dx + a.by * Dy + a.bz * Dz;   // Zeeman
+    dch -= a.bx * Dx + a.by * Dy + a.bz * Dz;   // Zeeman
     {   // longitudinal (Eq. 7 exponent); qB - qA = ((1+fm1)^2 - 1) qA
         const float dq = fm1 * (2.0f + fm1) * qA;
         if (C.below != 0.0f) dF += C.la * dq * (2.0f * (float)(qAd - C.me2) + dq);
         else dF += dq * (C.lb + C.lbc * (2.0f * qA + dq));
     }
-    if (DMG) dF -= a.cdm * (Dx * hx + Dy * hy + Dz * hz);   // frozen demag field (Eq. 14)
+    if (DMG) dch -= a.cdm * (Dx * hx + Dy * hy + Dz * hz);   // frozen demag field (Eq. 14)
+    if (TS) dF += C.tsc * dFc;
     // 4) accept with min{1, (mB/mA)^k exp(-dF/kT)} (Eq. 5): ln u3 < k ln f - dF
     const float kexp = EXACT ? 3.0f : 4.0f;
     const bool ok = (kexp * l2f - dF * 1.44269504088896341f) > __builtin_amdgcn_logf(u3);
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(256, B ? 3 : 4) void k_pass4(ChainDesc d0, const Ch
             const unsigned pnat = pbase + 2u * k;
             const uint4 r = philox4x32_10(make_uint4(pnat, (uint32_t)sweep, a.chain, (uint32_t)colour), a.k0, a.k1);
             float ox, oy, oz;
-            const bool ok = cell_move<EXACT, DMI, DMG>(a, C, r, omc, comp(A[0], k), comp(A[1], k), comp(A[2], k), nb,
+            const bool ok = cell_move<EXACT, DMI, DMG, false>(a, C, r, omc, comp(A[0], k), comp(A[1], k), comp(A[2], k), nb,
                                                        DMG ? comp(H[0], k) : 0.f, DMG ? comp(H[1], k) : 0.f,
                                                        DMG ? comp(H[2], k) : 0.f, ox, oy, oz);
             if (k == 0) { OUT[0].x = ox; OUT[1].x = oy; OUT[2].x = oz; }
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(256) void k_pass1(ChainDesc d0, const ChainDesc* __
             const unsigned pnat = (unsigned)((z * a.ny + y) * a.nx + x);
             const uint4 r = philox4x32_10(make_uint4(pnat, (uint32_t)sweep, a.chain, (uint32_t)colour), a.k0, a.k1);
             float ox, oy, oz;
-            const bool ok = cell_move<EXACT, DMI, DMG>(a, C, r, omc, own[idx], own[Nc + idx], own[2 * Nc + idx], nb,
+            const bool ok = cell_move<EXACT, DMI, DMG, CLS>(a, C, r, omc, own[idx], own[Nc + idx], own[2 * Nc + idx], nb,
                                                        hx, hy, hz, ox, oy, oz);
             own[idx] = ox;
             own[Nc + idx] = oy;

@@ -64,6 +64,7 @@ _SIGS = {
                                  C.c_void_p, C.c_double]),
     "mmc_set_field": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "mmc_set_temperature": (C.c_int, [C.c_void_p, C.c_double]),
+    "mmc_set_grain_temperatures": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32]),
     "mmc_set_m": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_get_m": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_sweep": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -178,6 +179,14 @@ class Chain:
 
     def set_temperature(self, T):
         _check(lib().mmc_set_temperature(self._h, float(T)))
+
+    def set_grain_temperatures(self, T_of_grain):
+        """Per-grain temperatures (K) of a non-uniform temperature profile, or None."""
+        if T_of_grain is None:
+            _check(lib().mmc_set_grain_temperatures(self._h, None, 0))
+            return
+        t = np.ascontiguousarray(T_of_grain, dtype=np.float64)
+        _check(lib().mmc_set_grain_temperatures(self._h, t.ctypes.data, int(t.size)))
 
     def set_m(self, m):
         """m: numpy (3, N) float32 (host) or torch CUDA tensor (3, N) float32 (device)."""

@@ -154,3 +154,36 @@ def test_energy_matches_oracle(O, mmc, demag):
     scale = np.abs(Eo).sum()
     assert np.abs(terms - Eo).max() < 2e-6 * scale, (terms, Eo)
     assert abs(E - Eo.sum()) < 2e-6 * scale
+
+
+@pytest.mark.parametrize("with_demag", [False, True])
+def test_subsweep_decisions_temperature_profile(O, mmc, with_demag):
+    """Non-uniform temperature profile: grains at their own temperatures
+    (below and above Tc), DMI, grain-boundary exchange scale, optional demag."""
+    grid, cell = (30, 22, 2), (4e-9, 4e-9, 3e-9)
+    N = int(np.prod(grid))
+    gid, ng = workloads.voronoi_grains(grid, cell, 9e-9, 5)
+    ea, K1, K2, Tc = workloads.grain_properties(ng, seed=6)
+    Tg = np.linspace(350.0, 760.0, ng)             # a temperature gradient across the grains
+    kw = dict(Ms0=1e6, A0=1e-11, K1=5e5, Tc=700.0, T=500.0, B=(0.0, 0.05, 0.2), D0=1.2e-3, seed=13, chain_id=2)
+    ch = mmc.Chain(grid, cell, demag=with_demag, **kw)
+    ch.set_grains(gid, ea, K1, K2, Tc, 0.3)
+    ch.set_grain_temperatures(Tg)
+    ref = O.System(grid, cell, demag=with_demag, cls=gid, ea=ea, K1s=K1, K2s=K2, Tcs=Tc, bscale=0.3, Tcl=Tg, **kw)
+    c = ref.coeffs()
+    for trial in range(3):
+        m0 = workloads.random_state(N, seed=40 + trial, lmin=0.3, lmax=1.0)
+        h = ref.demag(m0.astype(np.float32).astype(np.float64)) if with_demag else None
+        for colour in (0, 1):
+            _decision_check(O, ch, ref, m0, sweep=77 + trial, colour=colour, cone=[25, 90, 180][trial], h=h)
+    # energy with the profile: the longitudinal and anisotropy terms at each grain's own kT
+    m = workloads.random_state(N, seed=9, lmin=0.3, lmax=0.9)
+    ch.set_m(m)
+    E, terms = ch.energy()
+    Eo = ref.energy(m.astype(np.float64))
+    scale = np.abs(Eo).sum()
+    assert np.abs(terms - Eo).max() < 2e-6 * scale, (terms, Eo)
+    # NULL profile: back to the chain temperature
+    ch.set_grain_temperatures(None)
+    with pytest.raises(mmc.MMCError):
+        ch.set_grain_temperatures(np.ones(ng + 1) * 300.0)

@@ -183,3 +183,12 @@ def test_macrospins_at_their_own_temperatures(oracle_mod):
         m2, se_m2 = batch_se((sel ** 2).sum(axis=1).mean(axis=1))
         assert abs(mz - mz_q) < 4 * se_mz + 2e-3, (T, mz, mz_q, se_mz)
         assert abs(m2 - m2_q) < 4 * se_m2 + 2e-3, (T, m2, m2_q, se_m2)
+
+
+def test_gaussian_profile_classes():
+    import workloads
+    cls, T = workloads.gaussian_temperature_classes((64, 48, 2), (5e-9,) * 3, 150e-9, 400.0, 300.0, levels=8)
+    grid_T = T[cls].reshape(2, 48, 64)
+    assert cls.dtype == np.uint32 and cls.max() < 8 and np.all(np.diff(T) > 0)
+    assert np.array_equal(grid_T[0], grid_T[1])                  # the same profile in every layer
+    assert grid_T[0, 24, 32] == T[-1] and grid_T[0, 0, 0] == T[0]  # hottest at the centre, coolest at a corner

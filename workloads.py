@@ -1,9 +1,10 @@
 """Seeded synthetic inputs shared by the tests and the benchmark.
 
 Holds only input generation (grids, material constants, random states, grain
-maps, chain parameter draws); none of the Monte Carlo arithmetic.  Material and
-workload sizes follow the thin-film and granular-media settings of the paper's
-examples (nm cells, Tc of a few hundred K, Ms0 ~ 1 MA/m).
+maps, temperature profiles, chain parameter draws); none of the Monte Carlo
+arithmetic.  Material and workload sizes follow the thin-film and
+granular-media settings of the paper's examples (nm cells, Tc of a few hundred
+K, Ms0 ~ 1 MA/m).
 """
 import numpy as np
 
@@ -87,3 +88,21 @@ def batch_chain_params(n_chains, seed, Tc=700.0):
         out.append(dict(grid=BATCH_SIZES[int(rng.integers(0, len(BATCH_SIZES)))], T=float(rng.uniform(0.2, 1.2) * Tc),
                         B=(0.0, 0.0, float(rng.uniform(-0.5, 0.5))), chain_id=i))
     return out
+
+
+def gaussian_temperature_classes(grid, cell, width, T_centre, T_edge, levels=16):
+    """Gaussian temperature profile across the film plane (centre T_centre,
+    T_edge far out, full width `width` in metres between the 1/e points of the
+    rise), binned into `levels` classes of equal temperature.  Returns (class
+    id per cell in natural order, class temperatures); pass them as grains of
+    the material's constants and as grain temperatures."""
+    nx, ny, nz = grid
+    xs = (np.arange(nx) + 0.5 - nx / 2) * cell[0]
+    ys = (np.arange(ny) + 0.5 - ny / 2) * cell[1]
+    r2 = xs[None, :] ** 2 + ys[:, None] ** 2
+    T = T_edge + (T_centre - T_edge) * np.exp(-r2 / (width / 2) ** 2)
+    lo, hi = min(T_edge, T_centre), max(T_edge, T_centre)
+    k = np.clip(((T - lo) / max(hi - lo, 1e-300) * levels).astype(np.int64), 0, levels - 1)
+    T_of = lo + (np.arange(levels) + 0.5) * (hi - lo) / levels
+    cls = np.broadcast_to(k[None, :, :], (nz, ny, nx)).reshape(-1).astype(np.uint32)
+    return cls, T_of
