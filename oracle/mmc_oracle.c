@@ -16,7 +16,8 @@
  *   or_demag_*         FFT path == brute-force direct sum
  *   or_delta_F         equals E_total(after) - E_total(before) per term
  *   or_subsweep/or_run macrospin quadrature of the paper's Eq. 1 target
- *   or_energy          isotropy + closed forms on uniform states
+ *   or_energy          isotropy + closed forms on uniform states (uniaxial and
+ *                      the cubic <100>, <110>, <111> values), cubic symmetry
  */
 #include "mmc_oracle.h"
 #include <complex.h>
@@ -440,6 +441,42 @@ static double fl_kT(const or_class* c, double q) {   /* Eq. 7 exponent, q = m^2 
     return c->lb * q + c->lbc * q * q;
 }
 
+/* Anisotropy constants of class c in J/m^3 as the free energy uses them.  With
+ * kscale the temperature law of Sec. III applies: a term of order l scales as
+ * me^{l(l+1)/2}.  Uniaxial (Eq. 11): K1 is of order 2, K2 of order 4; cubic
+ * (Eq. 12): K1 of order 4, K2 of order 6. */
+static void an_consts(const or_sys* s, const or_class* c, int cp, double* k1, double* k2) {
+    *k1 = s->K1[cp];
+    *k2 = s->K2[cp];
+    if (s->kscale) {
+        int l1 = s->anis ? 4 : 2, l2 = s->anis ? 6 : 4;
+        *k1 *= pow(c->me, 0.5 * l1 * (l1 + 1));
+        *k2 *= pow(c->me, 0.5 * l2 * (l2 + 1));
+    }
+}
+
+/* Anisotropy energy density of one cell over its constants (J/m^3):
+ * uniaxial (Eq. 11) k1 (1 - (m.e)^2) + k2 (1 - (m.e)^2)^2 with m non-unit;
+ * cubic (Eq. 12) k1 (a^2 b^2 + a^2 g^2 + b^2 g^2) + k2 a^2 b^2 g^2 with a, b, g
+ * the direction cosines of m (components of m/|m| along the crystal axes). */
+static double an_density(const or_sys* s, int cp, double k1, double k2, const double mi[3]) {
+    if (!s->anis) {
+        const double* e = &s->ea[3 * cp];
+        double dd = mi[0] * e[0] + mi[1] * e[1] + mi[2] * e[2];
+        double u = 1.0 - dd * dd;
+        return k1 * u + k2 * u * u;
+    }
+    double L = sqrt(mi[0] * mi[0] + mi[1] * mi[1] + mi[2] * mi[2]);
+    if (L == 0.0) return 0.0;
+    double dc[3];
+    for (int a = 0; a < 3; ++a) {
+        const double* ax = &s->cax[9 * cp + 3 * a];
+        dc[a] = (mi[0] * ax[0] + mi[1] * ax[1] + mi[2] * ax[2]) / L;
+    }
+    double a2 = dc[0] * dc[0], b2 = dc[1] * dc[1], g2 = dc[2] * dc[2];
+    return k1 * (a2 * b2 + a2 * g2 + b2 * g2) + k2 * a2 * b2 * g2;
+}
+
 void or_delta_F(const or_sys* s, const or_class* cc, const double* m, const double* h,
                 int64_t p, const double mB[3], double out[6]) {
     int nx = s->nx, ny = s->ny, nz = s->nz;
@@ -481,12 +518,10 @@ void or_delta_F(const or_sys* s, const or_class* cc, const double* m, const doub
     double G[3] = {-dxmz, -dymz, dxmx + dymy};
     out[1] = -(2.0 * V * s->D0 / kT) * (D[0] * G[0] + D[1] * G[1] + D[2] * G[2]);
 
-    /* uniaxial anisotropy (Eq. 11), m non-unit, V on both terms */
-    const double* e = &s->ea[3 * cp];
-    double dA = mA[0] * e[0] + mA[1] * e[1] + mA[2] * e[2];
-    double dB = mB[0] * e[0] + mB[1] * e[1] + mB[2] * e[2];
-    double pA = dA * dA, pB = dB * dB;
-    out[2] = (V / kT) * (s->K1[cp] * (pA - pB) + s->K2[cp] * ((1 - pB) * (1 - pB) - (1 - pA) * (1 - pA)));
+    /* anisotropy (Eq. 11 or 12), V on both terms */
+    double k1, k2;
+    an_consts(s, c, cp, &k1, &k2);
+    out[2] = (V / kT) * (an_density(s, cp, k1, k2, mB) - an_density(s, cp, k1, k2, mA));
 
     /* Zeeman: -V Ms0 (mB - mA).B */
     out[3] = -(V * s->Ms0 / kT) * (D[0] * s->B[0] + D[1] * s->B[1] + D[2] * s->B[2]);
@@ -524,10 +559,9 @@ void or_energy(const or_sys* s, const or_class* cc, const double* m, const doubl
             if (d == 0) E[1] += -V * s->D0 * (mi[2] * mj[0] - mi[0] * mj[2]) / s->hx;
             if (d == 1) E[1] += -V * s->D0 * (mi[2] * mj[1] - mi[1] * mj[2]) / s->hy;
         }
-        const double* e = &s->ea[3 * cp];
-        double dd = mi[0] * e[0] + mi[1] * e[1] + mi[2] * e[2];
-        double u = 1.0 - dd * dd;
-        E[2] += V * (s->K1[cp] * u + s->K2[cp] * u * u);
+        double k1, k2;
+        an_consts(s, &cc[cp], cp, &k1, &k2);
+        E[2] += V * an_density(s, cp, k1, k2, mi);
         E[3] += -V * s->Ms0 * (mi[0] * s->B[0] + mi[1] * s->B[1] + mi[2] * s->B[2]);
         E[4] += OR_KB * T_of(s, cp) * fl_kT(&cc[cp], mi[0] * mi[0] + mi[1] * mi[1] + mi[2] * mi[2]);
         if (h) E[5] += -0.5 * OR_MU0 * V * s->Ms0 * s->Ms0 * (mi[0] * h[p] + mi[1] * h[N + p] + mi[2] * h[2 * N + p]);

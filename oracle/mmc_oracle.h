@@ -76,6 +76,12 @@ typedef struct {
                                  * every class at T.  A move at a cell of class c is judged at T_c: every
                                  * term of its dF is divided by kB*T_c (local detailed balance), and the
                                  * class's me, chi, sigma and Eq. 7 coefficients are taken at T_c. */
+    int32_t anis;               /* 0: uniaxial anisotropy (Eq. 11) about ea with constants K1, K2;
+                                 * 1: cubic anisotropy (Eq. 12) in place of it: K1, K2 are then the 4th and
+                                 * 6th order cubic constants and cax holds the crystal axes */
+    const double* cax;          /* anis 1: 9*nclass, three orthonormal cubic axes per class */
+    int32_t kscale;             /* 1: each anisotropy constant of order l is multiplied by me^{l(l+1)/2}
+                                 * (Sec. III, Fe film), me of the class at its temperature; 0: as given */
 } or_sys;
 
 /* Fill cls_out[nclass]. */

@@ -44,7 +44,8 @@ class OrSys(C.Structure):
                 ("seed", C.c_uint64), ("chain_id", C.c_uint32), ("sigma_fixed", C.c_double),
                 ("nclass", C.c_int32), ("cls", C.POINTER(C.c_uint32)), ("ea", C.POINTER(C.c_double)),
                 ("K1", C.POINTER(C.c_double)), ("K2", C.POINTER(C.c_double)), ("Tc", C.POINTER(C.c_double)),
-                ("bscale", C.c_double), ("Tcl", C.POINTER(C.c_double))]
+                ("bscale", C.c_double), ("Tcl", C.POINTER(C.c_double)),
+                ("anis", C.c_int32), ("cax", C.POINTER(C.c_double)), ("kscale", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -156,7 +157,8 @@ class System:
 
     def __init__(self, grid, cell, Ms0, A0, K1, Tc, T, D0=0.0, K2=0.0, easy_axis=(0, 0, 1), B=(0, 0, 0),
                  mf=1, mu=MUB, lenmode=0, demag=False, refresh_per_sweep=2, seed=0, chain_id=0,
-                 sigma_fixed=0.0, cls=None, ea=None, K1s=None, K2s=None, Tcs=None, bscale=1.0, Tcl=None):
+                 sigma_fixed=0.0, cls=None, ea=None, K1s=None, K2s=None, Tcs=None, bscale=1.0, Tcl=None,
+                 cubic_axes=None, kscale=False):
         self.grid = tuple(int(v) for v in grid)
         self.cell = tuple(float(v) for v in cell)
         self.N = int(np.prod(self.grid))
@@ -192,6 +194,19 @@ class System:
         if self._Tcl is not None:
             assert self._Tcl.shape == (self.nclass,)
         s.Tcl = _ptr(self._Tcl) if self._Tcl is not None else C.POINTER(C.c_double)()
+        # cubic anisotropy (Eq. 12): (nclass, 3, 3) orthonormal crystal axes as rows (or (3, 3) for
+        # all classes); K1/K2 (K1s/K2s) are then the cubic constants.  kscale: me^{l(l+1)/2} law.
+        self._cax = None
+        if cubic_axes is not None:
+            ax = np.asarray(cubic_axes, dtype=np.float64)
+            if ax.shape == (3, 3):
+                ax = np.broadcast_to(ax, (self.nclass, 3, 3))
+            assert ax.shape == (self.nclass, 3, 3)
+            assert np.allclose(np.einsum("kij,klj->kil", ax, ax), np.eye(3), atol=1e-12)
+            self._cax = np.ascontiguousarray(ax)
+        s.anis = 0 if self._cax is None else 1
+        s.cax = _ptr(self._cax) if self._cax is not None else C.POINTER(C.c_double)()
+        s.kscale = int(bool(kscale))
         self.s = s
         self.refresh()
         self._plan = None
