@@ -16,7 +16,7 @@
  *     parallel.
  *   - dF sums exchange (Eq. 10, as the exact change of the bond energy
  *     sum_bonds V A0 |m_i - m_j|^2 / h^2), interfacial DMI (Eq. 15), uniaxial
- *     anisotropy (Eq. 11), Zeeman, the longitudinal LLB term (exponent of
+ *     or cubic anisotropy (Eqs. 11-12), Zeeman, the longitudinal LLB term (exponent of
  *     Eq. 7, parameterised by me(T), Eq. 9 and chi_par(T), Eq. 8) and the
  *     demag term with a frozen field (Sec. III, Eq. 14): H_d = -N*M by
  *     zero-padded FFT convolution with the cell-averaged (Newell) tensor,
@@ -148,6 +148,33 @@ mmc_status mmc_set_temperature(mmc_ctx* ctx, double T_kelvin);
  * MMC_ERR_STATE without grains, MMC_ERR_ARG for a count mismatch,
  * MMC_ERR_DOMAIN for a non-positive or non-finite temperature. */
 mmc_status mmc_set_grain_temperatures(mmc_ctx* ctx, const double* T_of_grain, uint32_t n_grains);
+
+/* Magnetocrystalline anisotropy form (Sec. II, Eqs. 11-12) and temperature law
+ * of its constants (Sec. III, Fe granular film). */
+typedef enum {
+    MMC_ANIS_UNIAXIAL = 0,   /* Eq. 11: K1 (1 - (m.e)^2) + K2 (1 - (m.e)^2)^2, m non-unit, per unit volume,
+                                with the easy axes and constants of mmc_material or mmc_set_grains */
+    MMC_ANIS_CUBIC = 1       /* Eq. 12 in place of Eq. 11: K1 (a^2 b^2 + a^2 g^2 + b^2 g^2) + K2 a^2 b^2 g^2,
+                                a, b, g the direction cosines of m along the crystal axes */
+} mmc_anis;
+/* Selects the anisotropy of every cell.  kind MMC_ANIS_UNIAXIAL: axes6, K1, K2
+ * must be NULL and n 0.  kind MMC_ANIS_CUBIC: n sets (host arrays), n = 1 for
+ * every cell or n = the grain count of mmc_set_grains for one set per grain:
+ * axes6[6k..6k+5] the first and second crystal axes of set k (any length, not
+ * parallel; the second is made orthogonal to the first, the third is their
+ * cross product), K1[k], K2[k] the 4th and 6th order cubic constants in
+ * J/m^3.  me_scaling = 1 multiplies each constant of order l by
+ * me^{l(l+1)/2}, me = me(T) of the grain at its own temperature (uniaxial K1,
+ * K2 of orders 2 and 4 by me^3 and me^10; cubic K1, K2 of orders 4 and 6 by
+ * me^10 and me^21; zero at and above Tc); 0 uses the constants as given.  The
+ * cubic form runs the per-cell colour pass (one cell per thread).  The state
+ * is kept; the setting survives mmc_set_field, mmc_set_temperature and
+ * mmc_set_grain_temperatures; mmc_set_grains returns to the uniaxial form
+ * without the temperature law.  Errors: MMC_ERR_ARG for an unknown kind or
+ * flag, NULL or extra arrays, a set count that is neither 1 nor the grain
+ * count, zero or parallel axes; MMC_ERR_DOMAIN for non-finite values. */
+mmc_status mmc_set_anisotropy(mmc_ctx* ctx, int32_t kind, const double* axes6, const double* K1, const double* K2,
+                              uint32_t n, int32_t me_scaling);
 
 /* State in/out, natural SoA layout (3*N floats).  set: every |m_i| > 0 and
  * finite, else MMC_ERR_DOMAIN.  get synchronises the stream. */

@@ -61,6 +61,12 @@ struct mmc_ctx {
     bool has_classes = false;
     std::vector<double> ea, K1, K2, Tc;
     std::vector<double> Tg;      // per-grain temperatures (empty: every grain at run.T)
+    // anisotropy form: uniaxial (ea, K1, K2 above) or cubic (ncub sets of axes and constants:
+    // 1 for every class or one per class); kscale: temperature law of the constants
+    bool cubic = false;
+    bool kscale = false;
+    int ncub = 0;
+    std::vector<double> cax, cK1, cK2;
     double bscale = 1.0;
     std::vector<ClassCoef> ctab;
     ClassCoef* d_ctab = nullptr;
@@ -141,10 +147,15 @@ static Chains single(const mmc_ctx* ctx) { return Chains{make_desc(ctx), nullptr
 
 static mmc_status upload_classes(mmc_ctx* ctx) {
     ctx->ctab.resize(ctx->nclass);
-    for (int k = 0; k < ctx->nclass; ++k)
-        ctx->ctab[k] = class_coef(ctx->mat, ctx->Tg.empty() ? ctx->run.T : ctx->Tg[k], ctx->run.T, ctx->V,
-                                  ctx->K1[k], ctx->K2[k], &ctx->ea[3 * k], ctx->Tc[k],
-                                  ctx->run.sigma_fixed, 1);
+    for (int k = 0; k < ctx->nclass; ++k) {
+        const double T = ctx->Tg.empty() ? ctx->run.T : ctx->Tg[k];
+        const int j = ctx->ncub == 1 ? 0 : k;
+        ctx->ctab[k] = ctx->cubic
+            ? class_coef(ctx->mat, T, ctx->run.T, ctx->V, ctx->cK1[j], ctx->cK2[j], &ctx->ea[3 * k], &ctx->cax[6 * j],
+                         ctx->kscale, ctx->Tc[k], ctx->run.sigma_fixed)
+            : class_coef(ctx->mat, T, ctx->run.T, ctx->V, ctx->K1[k], ctx->K2[k], &ctx->ea[3 * k], nullptr,
+                         ctx->kscale, ctx->Tc[k], ctx->run.sigma_fixed);
+    }
     if (ctx->d_ctab) { HIPCK(hipFree(ctx->d_ctab)); ctx->d_ctab = nullptr; }
     HIPCK(hipMalloc(&ctx->d_ctab, sizeof(ClassCoef) * ctx->nclass));
     HIPCK(hipMemcpyAsync(ctx->d_ctab, ctx->ctab.data(), sizeof(ClassCoef) * ctx->nclass, hipMemcpyHostToDevice,
@@ -199,7 +210,8 @@ static mmc_status enqueue_core(mmc_ctx* c0, const Chains& ch, int n, hipStream_t
                 }
             }
             HIPCK(mark(-1));
-            HIPCK(launch_pass(c0->args, c0->has_classes, c0->demag, exact, dmi, ch, c, true, c0->fp_shift, nullptr, st));
+            HIPCK(launch_pass(c0->args, c0->has_classes, c0->demag, exact, dmi, c0->cubic, ch, c, true, c0->fp_shift,
+                              nullptr, st));
             HIPCK(mark(3));
         }
         HIPCK(mark(-1));
@@ -393,6 +405,9 @@ mmc_status mmc_set_grains(mmc_ctx* ctx, const uint32_t* grain_of_cell, uint32_t 
     ctx->bscale = boundary_exchange_scale;
     ctx->has_classes = true;
     ctx->Tg.clear();
+    ctx->cubic = false;
+    ctx->kscale = false;
+    ctx->ncub = 0;
     if (!ctx->d_cid) HIPCK(hipMalloc(&ctx->d_cid, sizeof(uint32_t) * 2 * (size_t)ctx->Nc));
     HIPCK(hipMemcpy(ctx->d_cid, split.data(), sizeof(uint32_t) * split.size(), hipMemcpyHostToDevice));
     update_args(ctx);
@@ -437,6 +452,45 @@ mmc_status mmc_set_grain_temperatures(mmc_ctx* ctx, const double* T_of_grain, ui
     if (T_of_grain) ctx->Tg.assign(T_of_grain, T_of_grain + n_grains);
     else ctx->Tg.clear();
     update_args(ctx);
+    return upload_classes(ctx);
+}
+
+mmc_status mmc_set_anisotropy(mmc_ctx* ctx, int32_t kind, const double* axes6, const double* K1, const double* K2,
+                              uint32_t n, int32_t me_scaling) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (me_scaling != 0 && me_scaling != 1) return fail(MMC_ERR_ARG, "me_scaling must be 0 or 1");
+    if (kind == MMC_ANIS_UNIAXIAL) {
+        if (axes6 || K1 || K2 || n != 0) return fail(MMC_ERR_ARG, "uniaxial form takes no axes or constants");
+    } else if (kind == MMC_ANIS_CUBIC) {
+        if (!axes6 || !K1 || !K2) return fail(MMC_ERR_ARG, "NULL cubic axes or constants");
+        if (n != 1 && (int64_t)n != (int64_t)ctx->nclass)
+            return fail(MMC_ERR_ARG, "%u cubic sets: need 1 or one per grain (%d)", n, ctx->nclass);
+        for (uint32_t k = 0; k < n; ++k) {
+            const double* a = axes6 + 6 * (size_t)k;
+            const double n1 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2], n2 = a[3] * a[3] + a[4] * a[4] + a[5] * a[5];
+            const double cx = a[1] * a[5] - a[2] * a[4], cy = a[2] * a[3] - a[0] * a[5], cz = a[0] * a[4] - a[1] * a[3];
+            bool fin = std::isfinite(K1[k]) && std::isfinite(K2[k]);
+            for (int q = 0; q < 6; ++q) fin = fin && std::isfinite(a[q]);
+            if (!fin) return fail(MMC_ERR_DOMAIN, "cubic set %u: constants and axes must be finite", k);
+            if (!(n1 > 0) || !(n2 > 0) || !(cx * cx + cy * cy + cz * cz > 1e-12 * n1 * n2))
+                return fail(MMC_ERR_ARG, "cubic set %u: axes zero or parallel", k);
+        }
+    } else {
+        return fail(MMC_ERR_ARG, "unknown anisotropy kind %d", kind);
+    }
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    ctx->cubic = kind == MMC_ANIS_CUBIC;
+    ctx->kscale = me_scaling != 0;
+    ctx->ncub = ctx->cubic ? (int)n : 0;
+    if (ctx->cubic) {
+        ctx->cax.assign(axes6, axes6 + 6 * (size_t)n);
+        ctx->cK1.assign(K1, K1 + n);
+        ctx->cK2.assign(K2, K2 + n);
+    } else {
+        ctx->cax.clear(); ctx->cK1.clear(); ctx->cK2.clear();
+    }
+    ctx->version++;
     return upload_classes(ctx);
 }
 
@@ -568,7 +622,7 @@ mmc_status mmc_energy(mmc_ctx* ctx, double* E_total, double E_terms[6]) {
         ctx->epart_n = blocks;
     }
     int nb = 0;
-    HIPCK(launch_energy(ctx->args, ctx->has_classes, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->demag ? ctx->d_h : nullptr,
+    HIPCK(launch_energy(ctx->args, ctx->has_classes, ctx->cubic, ctx->d_ctab, ctx->d_cid, ctx->d_m, ctx->demag ? ctx->d_h : nullptr,
                         ctx->d_epart, ctx->stream, &nb));
     std::vector<double> part(6 * (size_t)nb);
     HIPCK(hipMemcpyAsync(part.data(), ctx->d_epart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, ctx->stream));
@@ -592,7 +646,7 @@ mmc_status mmc_subsweep(mmc_ctx* ctx, int32_t colour, const float* h_in, uint8_t
     HIPCK(hipMemsetAsync(acc_out, 255, (size_t)ctx->N, ctx->stream));
     if (h_in) HIPCK(launch_to_split(ctx->args, h_in, ctx->d_h, ctx->stream));
     HIPCK(launch_pass(ctx->args, ctx->has_classes, h_in != nullptr, ctx->run.lenmove == MMC_LEN_EXACT,
-                      ctx->mat.D0 != 0.0, single(ctx), colour, false, ctx->fp_shift, acc_out, ctx->stream));
+                      ctx->mat.D0 != 0.0, ctx->cubic, single(ctx), colour, false, ctx->fp_shift, acc_out, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
     return MMC_OK;
 }
@@ -690,7 +744,7 @@ static bool same_shape(const mmc_ctx* a, const mmc_ctx* c) {
     return a->g.nx == c->g.nx && a->g.ny == c->g.ny && a->g.nz == c->g.nz && a->cs.hx == c->cs.hx &&
            a->cs.hy == c->cs.hy && a->cs.hz == c->cs.hz && a->has_classes == c->has_classes &&
            a->demag == c->demag && (!a->demag || a->run.refresh_per_sweep == c->run.refresh_per_sweep) &&
-           a->run.lenmove == c->run.lenmove && (a->mat.D0 != 0.0) == (c->mat.D0 != 0.0);
+           a->run.lenmove == c->run.lenmove && (a->mat.D0 != 0.0) == (c->mat.D0 != 0.0) && a->cubic == c->cubic;
 }
 
 // Regroups the chains and uploads each group's descriptors.

@@ -69,7 +69,7 @@ __device__ __forceinline__ void load_m(const SweepArgs& a, const float* m, int x
 template <bool CLS>
 __global__ __launch_bounds__(256) void k_energy(SweepArgs a, const ClassCoef* __restrict__ ctab, const uint32_t* __restrict__ cid,
                                                 const float* __restrict__ m, const float* __restrict__ h,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, int cubic) {
     const long long N = (long long)a.nx * a.ny * a.nz;
     double e[6] = {0, 0, 0, 0, 0, 0};
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < N; p += (long long)gridDim.x * blockDim.x) {
@@ -98,11 +98,22 @@ __global__ __launch_bounds__(256) void k_energy(SweepArgs a, const ClassCoef* __
             if (d == 0) e[1] += -(double)a.cdx * ((double)mz * qx - (double)mx * qz);
             if (d == 1) e[1] += -(double)a.cdy * ((double)mz * qy - (double)my * qz);
         }
-        const double dd = (double)mx * C.ex + (double)my * C.ey + (double)mz * C.ez;
-        const double u = 1.0 - dd * dd;
         // (class terms are in units of the class's kT: 1/tsc converts to the chain's kT0)
         const double cs = CLS ? 1.0 / (double)C.tsc : 1.0;
-        e[2] += cs * ((double)C.ka1 * u + (double)C.ka2 * u * u);
+        if (cubic) {   // Eq. 12 on the direction cosines of m along the crystal axes
+            const double L = sqrt((double)mx * mx + (double)my * my + (double)mz * mz);
+            if (L > 0.0) {
+                const double p1 = ((double)mx * C.ex + (double)my * C.ey + (double)mz * C.ez) / L;
+                const double p2 = ((double)mx * C.fx + (double)my * C.fy + (double)mz * C.fz) / L;
+                const double p3 = ((double)mx * C.gx + (double)my * C.gy + (double)mz * C.gz) / L;
+                const double s1 = p1 * p1, s2 = p2 * p2, s3 = p3 * p3;
+                e[2] += cs * ((double)C.ka1 * (s1 * s2 + s1 * s3 + s2 * s3) + (double)C.ka2 * s1 * s2 * s3);
+            }
+        } else {       // Eq. 11, m non-unit
+            const double dd = (double)mx * C.ex + (double)my * C.ey + (double)mz * C.ez;
+            const double u = 1.0 - dd * dd;
+            e[2] += cs * ((double)C.ka1 * u + (double)C.ka2 * u * u);
+        }
         e[3] += -((double)a.bx * mx + (double)a.by * my + (double)a.bz * mz);
         const double q = (double)mx * mx + (double)my * my + (double)mz * mz;
         if (C.below != 0.0f) { const double dq = q - C.me2; e[4] += cs * (double)C.la * dq * dq; }
@@ -157,13 +168,14 @@ hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_energy(const SweepArgs& a, bool classes, const ClassCoef* ctab, const uint32_t* cid,
+hipError_t launch_energy(const SweepArgs& a, bool classes, bool cubic, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out) {
     const long long N = (long long)a.nx * a.ny * a.nz;
     const int blocks = (int)std::min<long long>((N + 255) / 256, 2048);
     *nblk_out = blocks;
-    if (classes) hipLaunchKernelGGL(k_energy<true>, dim3(blocks), dim3(256), 0, s, a, ctab, cid, m, h, part);
-    else hipLaunchKernelGGL(k_energy<false>, dim3(blocks), dim3(256), 0, s, a, ctab, cid, m, h, part);
+    const int cb = cubic ? 1 : 0;
+    if (classes) hipLaunchKernelGGL(k_energy<true>, dim3(blocks), dim3(256), 0, s, a, ctab, cid, m, h, part, cb);
+    else hipLaunchKernelGGL(k_energy<false>, dim3(blocks), dim3(256), 0, s, a, ctab, cid, m, h, part, cb);
     return hipGetLastError();
 }
 

@@ -21,12 +21,14 @@ struct alignas(16) ClassCoef {
     float sigma;     // length-move width
     float ln1ps;     // ln(1 + sigma)
     float m0;        // initial length
-    float ex, ey, ez;  // easy axis (unit)
-    float ka1, ka2;  // V K1/kT, V K2/kT
+    float ex, ey, ez;  // uniaxial: easy axis; cubic: first crystal axis (unit)
+    float ka1, ka2;  // V K1/kT, V K2/kT (uniaxial Eq. 11 or cubic Eq. 12 constants, temperature law applied)
     float tsc;       // T0/T of the class: factor on the terms the chain keeps in units of kT0
                      // (exchange, DMI, Zeeman, demag); 1 at a uniform temperature
+    float fx, fy, fz;  // cubic: second crystal axis
+    float gx, gy, gz;  // cubic: third crystal axis (e x f)
 };
-static_assert(sizeof(ClassCoef) == 64, "ClassCoef layout");
+static_assert(sizeof(ClassCoef) == 96, "ClassCoef layout");
 
 // Uniform per-chain constants of a colour pass (kT units).
 struct SweepArgs {
@@ -64,8 +66,11 @@ struct SweepAccum {
 // Host-side physics setup (setup.cpp).
 void meanfield(int model, double T, double Tc, double mu, double* me, double* inv_chi);
 // T: the class's temperature; T0: the chain's reference temperature (kT0 units of SweepArgs).
+// cax6 == NULL: uniaxial anisotropy about ea with constants K1, K2; else cubic, K1 and K2 the cubic
+// constants and cax6 the first and second crystal axes (any length, not parallel).  kscale: each
+// constant of order l times me^{l(l+1)/2}, me of the class at T.
 ClassCoef class_coef(const mmc_material& mat, double T, double T0, double V, double K1, double K2, const double* ea,
-                     double Tc, double sigma_fixed, int nthreads);
+                     const double* cax6, bool kscale, double Tc, double sigma_fixed);
 // Demag tensor spectrum K[kx][ky'][q][dz] (kx in [0, Px/2], ky' in [0, Py/2],
 // q = xx,yy,zz,xy,xz,yz, dz in [0,nz)), including the -1/(Px Py) factor.
 void tensor_spectrum(int nx, int ny, int nz, double hx, double hy, double hz, int Px, int Py,
@@ -125,12 +130,11 @@ hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p,
 hipError_t launch_x_twiddles(const DemagPlan& p, float2* tw, hipStream_t s);
 hipError_t launch_demag(const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask, const float2* tw,
                         hipStream_t s);
-hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, const Chains& c,
+hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, bool cubic, const Chains& c,
                        int colour, bool stats, int shift, uint8_t* dec, hipStream_t s);
 hipError_t launch_end_sweep(const Chains& c, int shift, long long N, double* series, unsigned long long rec_base,
                             hipStream_t s);
-int pass_blocks(const SweepArgs& a, bool classes);
-hipError_t launch_energy(const SweepArgs& a, bool classes, const ClassCoef* ctab, const uint32_t* cid,
+hipError_t launch_energy(const SweepArgs& a, bool classes, bool cubic, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out);
 hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s);
 

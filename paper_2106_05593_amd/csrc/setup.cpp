@@ -84,7 +84,7 @@ static double mean_m2_above(double lb, double lbc) {
 }
 
 ClassCoef class_coef(const mmc_material& mat, double T, double T0, double V, double K1, double K2, const double* ea,
-                     double Tc, double sigma_fixed, int /*nthreads*/) {
+                     const double* cax6, bool kscale, double Tc, double sigma_fixed) {
     ClassCoef c{};
     double me = 0.0, ic = 0.0;
     meanfield(mat.mf, T, Tc, mat.mu_atomic, &me, &ic);
@@ -112,10 +112,35 @@ ClassCoef class_coef(const mmc_material& mat, double T, double T0, double V, dou
     if (sigma_fixed > 0) sigma = sigma_fixed;
     c.sigma = (float)sigma;
     c.ln1ps = (float)std::log1p(sigma);
-    const double en = std::sqrt(ea[0] * ea[0] + ea[1] * ea[1] + ea[2] * ea[2]);
-    c.ex = (float)(ea[0] / en); c.ey = (float)(ea[1] / en); c.ez = (float)(ea[2] / en);
-    c.ka1 = (float)(V * K1 / kT);
-    c.ka2 = (float)(V * K2 / kT);
+    if (cax6) {
+        // crystal axes: e = a1/|a1|, f = a2 made orthogonal to e, g = e x f
+        double e[3], f[3], g[3];
+        const double n1 = std::sqrt(cax6[0] * cax6[0] + cax6[1] * cax6[1] + cax6[2] * cax6[2]);
+        for (int k = 0; k < 3; ++k) e[k] = cax6[k] / n1;
+        const double pr = cax6[3] * e[0] + cax6[4] * e[1] + cax6[5] * e[2];
+        for (int k = 0; k < 3; ++k) f[k] = cax6[3 + k] - pr * e[k];
+        const double n2 = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        for (int k = 0; k < 3; ++k) f[k] /= n2;
+        g[0] = e[1] * f[2] - e[2] * f[1];
+        g[1] = e[2] * f[0] - e[0] * f[2];
+        g[2] = e[0] * f[1] - e[1] * f[0];
+        c.ex = (float)e[0]; c.ey = (float)e[1]; c.ez = (float)e[2];
+        c.fx = (float)f[0]; c.fy = (float)f[1]; c.fz = (float)f[2];
+        c.gx = (float)g[0]; c.gy = (float)g[1]; c.gz = (float)g[2];
+    } else {
+        const double en = std::sqrt(ea[0] * ea[0] + ea[1] * ea[1] + ea[2] * ea[2]);
+        c.ex = (float)(ea[0] / en); c.ey = (float)(ea[1] / en); c.ez = (float)(ea[2] / en);
+    }
+    // temperature law of the anisotropy constants (Sec. III, Fe film): order l
+    // scales as me^{l(l+1)/2}; uniaxial orders 2 and 4, cubic orders 4 and 6
+    double s1 = 1.0, s2 = 1.0;
+    if (kscale) {
+        const int l1 = cax6 ? 4 : 2, l2 = cax6 ? 6 : 4;
+        s1 = std::pow(me, 0.5 * l1 * (l1 + 1));
+        s2 = std::pow(me, 0.5 * l2 * (l2 + 1));
+    }
+    c.ka1 = (float)(V * K1 * s1 / kT);
+    c.ka2 = (float)(V * K2 * s2 / kT);
     c.tsc = (float)(T0 / T);
     return c;
 }

@@ -26,7 +26,8 @@ struct Nbr {          // one neighbour: value and exchange weight (0 when absent
 // TS: per-class temperatures; the exchange, DMI, Zeeman and demag terms are
 // formed in units of the chain's kT0 and scaled by C.tsc = T0/T of the class,
 // so every term of dF is in units of the cell's own kT (local detailed balance).
-template <bool EXACT, bool DMI, bool DMG, bool TS>
+// CUB: cubic anisotropy (Eq. 12) in place of the uniaxial form (Eq. 11).
+template <bool EXACT, bool DMI, bool DMG, bool TS, bool CUB = false>
 __device__ __forceinline__ bool cell_move(const SweepArgs& a, const ClassCoef& C, const uint4 r, const float omc,
                                           const float ax, const float ay, const float az, const Nbr (&nb)[6],
                                           const float hx, const float hy, const float hz,
@@ -68,7 +69,14 @@ __device__ __forceinline__ bool cell_move(const SweepArgs& a, const ClassCoef& C
     if (DMI)   // interfacial DMI (Eq. 15), central differences
         dch -= a.cdx * (Dz * (nb[1].x - nb[0].x) - Dx * (nb[1].z - nb[0].z)) +
                a.cdy * (Dz * (nb[3].y - nb[2].y) - Dy * (nb[3].z - nb[2].z));
-    {   // uniaxial anisotropy (Eq. 11)
+    if (CUB) {   // cubic anisotropy (Eq. 12): squared direction cosines along the crystal axes e, f, g
+        const float a1 = nx_ * C.ex + ny_ * C.ey + nz_ * C.ez, a2 = nx_ * C.fx + ny_ * C.fy + nz_ * C.fz;
+        const float a3 = nx_ * C.gx + ny_ * C.gy + nz_ * C.gz;
+        const float b1 = nbx * C.ex + nby * C.ey + nbz * C.ez, b2 = nbx * C.fx + nby * C.fy + nbz * C.fz;
+        const float b3 = nbx * C.gx + nby * C.gy + nbz * C.gz;
+        const float pa = a1 * a1, qa = a2 * a2, ra = a3 * a3, pb = b1 * b1, qb = b2 * b2, rb = b3 * b3;
+        dF += C.ka1 * ((pb * (qb + rb) + qb * rb) - (pa * (qa + ra) + qa * ra)) + C.ka2 * (pb * qb * rb - pa * qa * ra);
+    } else {   // uniaxial anisotropy (Eq. 11)
         const float dA = ax * C.ex + ay * C.ey + az * C.ez;
         const float dB = bx * C.ex + by * C.ey + bz * C.ez;
         const float dd = Dx * C.ex + Dy * C.ey + Dz * C.ez;
@@ -273,8 +281,9 @@ __global__ __launch_bounds__(256, B ? 3 : 4) void k_pass4(ChainDesc d0, const Ch
     if (acc) block_stats(sx, sy, sz, sq, nacc, acc, shift, lb);
 }
 
-// C = 1: any grid, optional per-cell material classes (grains).
-template <bool CLS, bool DMG, bool EXACT, bool DMI, bool B>
+// C = 1: any grid, optional per-cell material classes (grains), uniaxial or
+// cubic anisotropy (CUB).
+template <bool CLS, bool DMG, bool EXACT, bool DMI, bool CUB, bool B>
 __global__ __launch_bounds__(256) void k_pass1(ChainDesc d0, const ChainDesc* __restrict__ dl, int colour, int stats,
                                                int shift, uint8_t* __restrict__ dec) {
     const ChainDesc& cd = chain_at<B>(d0, dl, blockIdx.y);
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(256) void k_pass1(ChainDesc d0, const ChainDesc* __
             const unsigned pnat = (unsigned)((z * a.ny + y) * a.nx + x);
             const uint4 r = philox4x32_10(make_uint4(pnat, (uint32_t)sweep, a.chain, (uint32_t)colour), a.k0, a.k1);
             float ox, oy, oz;
-            const bool ok = cell_move<EXACT, DMI, DMG, CLS>(a, C, r, omc, own[idx], own[Nc + idx], own[2 * Nc + idx], nb,
+            const bool ok = cell_move<EXACT, DMI, DMG, CLS, CUB>(a, C, r, omc, own[idx], own[Nc + idx], own[2 * Nc + idx], nb,
                                                        hx, hy, hz, ox, oy, oz);
             own[idx] = ox;
             own[Nc + idx] = oy;
@@ -350,34 +359,39 @@ int pass_blocks(const SweepArgs& a, bool classes) {
     return (int)((threads + 255) / 256);
 }
 
-template <bool CLS, bool DMG, bool EXACT, bool DMI, bool B>
+template <bool CLS, bool DMG, bool EXACT, bool DMI, bool CUB, bool B>
 static void launch_pass_b(const SweepArgs& a, const Chains& c, int colour, int stats, int shift, uint8_t* dec,
                           hipStream_t s) {
-    const dim3 grid(pass_blocks(a, CLS), B ? c.n : 1);
-    if constexpr (!CLS) {
+    const dim3 grid(pass_blocks(a, CLS || CUB), B ? c.n : 1);
+    if constexpr (!CLS && !CUB) {
         if (pass_vec4(a, false)) {
             hipLaunchKernelGGL((k_pass4<DMG, EXACT, DMI, B>), grid, dim3(256), 0, s, c.one, c.many, colour, stats,
                                shift, dec);
             return;
         }
     }
-    hipLaunchKernelGGL((k_pass1<CLS, DMG, EXACT, DMI, B>), grid, dim3(256), 0, s, c.one, c.many, colour, stats, shift,
-                       dec);
+    hipLaunchKernelGGL((k_pass1<CLS, DMG, EXACT, DMI, CUB, B>), grid, dim3(256), 0, s, c.one, c.many, colour, stats,
+                       shift, dec);
 }
 
 template <bool CLS, bool DMG, bool EXACT, bool DMI>
-static void launch_pass_t(const SweepArgs& a, const Chains& c, int colour, int stats, int shift, uint8_t* dec,
-                          hipStream_t s) {
-    if (c.many) launch_pass_b<CLS, DMG, EXACT, DMI, true>(a, c, colour, stats, shift, dec, s);
-    else launch_pass_b<CLS, DMG, EXACT, DMI, false>(a, c, colour, stats, shift, dec, s);
+static void launch_pass_t(const SweepArgs& a, bool cubic, const Chains& c, int colour, int stats, int shift,
+                          uint8_t* dec, hipStream_t s) {
+    if (cubic) {
+        if (c.many) launch_pass_b<CLS, DMG, EXACT, DMI, true, true>(a, c, colour, stats, shift, dec, s);
+        else launch_pass_b<CLS, DMG, EXACT, DMI, true, false>(a, c, colour, stats, shift, dec, s);
+    } else {
+        if (c.many) launch_pass_b<CLS, DMG, EXACT, DMI, false, true>(a, c, colour, stats, shift, dec, s);
+        else launch_pass_b<CLS, DMG, EXACT, DMI, false, false>(a, c, colour, stats, shift, dec, s);
+    }
 }
 
-hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, const Chains& c,
-                       int colour, bool stats, int shift, uint8_t* dec, hipStream_t s) {
+hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact, bool dmi, bool cubic,
+                       const Chains& c, int colour, bool stats, int shift, uint8_t* dec, hipStream_t s) {
     const int key = (classes ? 8 : 0) | (demag ? 4 : 0) | (exact ? 2 : 0) | (dmi ? 1 : 0);
     const int st = stats ? 1 : 0;
 #define MMC_PASS(K, A_, B_, C_, D_) \
-    case K: launch_pass_t<A_, B_, C_, D_>(a, c, colour, st, shift, dec, s); break;
+    case K: launch_pass_t<A_, B_, C_, D_>(a, cubic, c, colour, st, shift, dec, s); break;
     switch (key) {
         MMC_PASS(0, false, false, false, false) MMC_PASS(1, false, false, false, true)
         MMC_PASS(2, false, false, true, false)  MMC_PASS(3, false, false, true, true)

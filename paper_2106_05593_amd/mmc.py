@@ -17,6 +17,7 @@ MMC_OK, MMC_ERR_ARG, MMC_ERR_DOMAIN, MMC_ERR_OOM, MMC_ERR_DEVICE, MMC_ERR_STATE,
 MMC_MF_LANGEVIN, MMC_MF_BRILLOUIN_HALF = 0, 1
 MMC_LEN_PAPER, MMC_LEN_EXACT = 0, 1
 MMC_DEMAG_OFF, MMC_DEMAG_FP32 = 0, 1
+MMC_ANIS_UNIAXIAL, MMC_ANIS_CUBIC = 0, 1
 MUB = 9.2740100783e-24
 
 
@@ -65,6 +66,8 @@ _SIGS = {
     "mmc_set_field": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "mmc_set_temperature": (C.c_int, [C.c_void_p, C.c_double]),
     "mmc_set_grain_temperatures": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32]),
+    "mmc_set_anisotropy": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                                     C.c_int32]),
     "mmc_set_m": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_get_m": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_sweep": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -187,6 +190,22 @@ class Chain:
             return
         t = np.ascontiguousarray(T_of_grain, dtype=np.float64)
         _check(lib().mmc_set_grain_temperatures(self._h, t.ctypes.data, int(t.size)))
+
+    def set_anisotropy(self, kind="uniaxial", axes=None, K1=None, K2=None, me_scaling=False):
+        """Anisotropy form: "uniaxial" (material / grain constants) or "cubic" with
+        axes (n, 2, 3) first and second crystal axes (or (2, 3) for every cell),
+        K1, K2 (n,) cubic constants in J/m^3; me_scaling: me^{l(l+1)/2} law."""
+        if kind == "uniaxial":
+            _check(lib().mmc_set_anisotropy(self._h, MMC_ANIS_UNIAXIAL, None, None, None, 0, int(bool(me_scaling))))
+            return
+        if kind != "cubic":
+            raise ValueError("kind must be 'uniaxial' or 'cubic'")
+        ax = np.ascontiguousarray(axes, dtype=np.float64).reshape(-1, 6)
+        n = ax.shape[0]
+        k1 = np.ascontiguousarray(np.broadcast_to(np.asarray(K1, dtype=np.float64), (n,)))
+        k2 = np.ascontiguousarray(np.broadcast_to(np.asarray(K2, dtype=np.float64), (n,)))
+        _check(lib().mmc_set_anisotropy(self._h, MMC_ANIS_CUBIC, ax.ctypes.data, k1.ctypes.data, k2.ctypes.data, n,
+                                        int(bool(me_scaling))))
 
     def set_m(self, m):
         """m: numpy (3, N) float32 (host) or torch CUDA tensor (3, N) float32 (device)."""

@@ -187,3 +187,77 @@ def test_subsweep_decisions_temperature_profile(O, mmc, with_demag):
     ch.set_grain_temperatures(None)
     with pytest.raises(mmc.MMCError):
         ch.set_grain_temperatures(np.ones(ng + 1) * 300.0)
+
+
+def _rot(seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))[None, :]
+    if np.linalg.det(q) < 0:
+        q[:, 2] *= -1
+    return q.T            # rows: orthonormal crystal axes
+
+
+@pytest.mark.parametrize("case", ["uniform", "grains_profile_demag"])
+def test_subsweep_decisions_cubic(O, mmc, case):
+    """Cubic anisotropy (Eq. 12) with the me^{l(l+1)/2} law: one crystal for
+    every cell (with DMI), or one per grain at per-grain temperatures with
+    demag.  Constants are large (V K1/kT ~ 3, V K2/kT ~ 10), the exchange is
+    weak and every length sits at its grain's m0, so the cubic term decides
+    many moves (on the oracle, dropping it changes 20-90 of ~900 decisions
+    per pass for the single crystal and 2-20 with grains and demag)."""
+    grid, cell = (34, 26, 2), (3e-9, 3e-9, 3e-9)
+    N = int(np.prod(grid))
+    kw = dict(Ms0=1.71e6, A0=2e-12, K1=0.0, Tc=1044.0, T=300.0, B=(0.05, 0.0, 0.02), seed=17, chain_id=3)
+    demag = case.endswith("demag")
+    if case == "uniform":
+        kw["D0"] = 1.0e-3
+        R = _rot(1)
+        ch = mmc.Chain(grid, cell, demag=False, **kw)
+        ch.set_anisotropy("cubic", R[:2], 5e5, -2e6, me_scaling=True)
+        ref = O.System(grid, cell, demag=False, cubic_axes=R, kscale=True, **dict(kw, K1=5e5, K2=-2e6))
+        L = np.full(N, ref.coeffs()["m0"])
+    else:
+        gid, ng = workloads.voronoi_grains(grid, cell, 9e-9, 8)
+        Rs = np.stack([_rot(100 + k) for k in range(ng)])
+        rng = np.random.default_rng(9)
+        Kc1 = rng.uniform(-4e5, 6e5, ng)
+        Kc2 = rng.uniform(-2e6, 2e6, ng)
+        Tc = rng.normal(1044.0, 30.0, ng)
+        Tg = np.where(np.arange(ng) % 5 == 4, 1080.0, np.linspace(250.0, 650.0, ng))   # every 5th above Tc
+        ea = np.tile([0.0, 0.0, 1.0], (ng, 1))
+        ch = mmc.Chain(grid, cell, demag=True, **kw)
+        ch.set_grains(gid, ea, np.zeros(ng), np.zeros(ng), Tc, 0.2)
+        ch.set_grain_temperatures(Tg)
+        ch.set_anisotropy("cubic", Rs[:, :2, :], Kc1, Kc2, me_scaling=True)
+        ref = O.System(grid, cell, demag=True, cls=gid, ea=ea, K1s=Kc1, K2s=Kc2, Tcs=Tc, bscale=0.2, Tcl=Tg,
+                       cubic_axes=Rs, kscale=True, **kw)
+        L = np.array([ref.coeffs(k)["m0"] for k in range(ng)])[gid]
+    for trial in range(3):
+        m0 = (workloads.random_state(N, seed=60 + trial, lmin=1.0, lmax=1.0) * L[None, :]).astype(np.float32)
+        h = ref.demag(m0.astype(np.float32).astype(np.float64)) if demag else None
+        for colour in (0, 1):
+            _decision_check(O, ch, ref, m0, sweep=91 + trial, colour=colour, cone=[20, 70, 180][trial], h=h)
+    m = workloads.random_state(N, seed=19, lmin=0.3, lmax=0.9)
+    ch.set_m(m)
+    E, terms = ch.energy()
+    Eo = ref.energy(m.astype(np.float64))
+    scale = np.abs(Eo).sum()
+    assert np.abs(terms - Eo).max() < 2e-6 * scale, (terms, Eo)
+    assert abs(terms[2] - Eo[2]) < 1e-5 * abs(Eo[2]), (terms[2], Eo[2])   # the cubic term on its own
+    # back to the uniaxial form (zero constants here): the anisotropy energy vanishes
+    ch.set_anisotropy("uniaxial")
+    assert abs(ch.energy()[1][2]) < 1e-30 + 1e-9 * scale
+
+
+def test_set_anisotropy_errors(mmc):
+    ch = mmc.Chain((8, 8, 1), (3e-9,) * 3, Ms0=1.71e6, A0=2.1e-11, K1=0.0, Tc=1044.0, T=300.0)
+    ax = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    for bad in (dict(axes=np.array([[1.0, 0, 0], [2.0, 0, 0]]), K1=1e4, K2=0.0),      # parallel axes
+                dict(axes=np.array([[0.0, 0, 0], [0.0, 1, 0]]), K1=1e4, K2=0.0),      # zero axis
+                dict(axes=np.tile(ax, (2, 1, 1)), K1=1e4, K2=0.0)):                   # 2 sets, no grains
+        with pytest.raises(mmc.MMCError):
+            ch.set_anisotropy("cubic", **bad)
+    with pytest.raises(mmc.MMCError):
+        ch.set_anisotropy("cubic", ax, np.nan, 0.0)
+    ch.set_anisotropy("cubic", ax, 1e4, 0.0)
+    ch.set_anisotropy("uniaxial", me_scaling=True)

@@ -56,32 +56,39 @@ def test_batch_equals_sequential(pkg):
 
 
 def test_batch_shape_groups_equal_sequential(pkg):
-    """Chains of one shape share launches (grains, DMI, adaptive cone, demag
-    once per sweep); a temperature change in one of them regroups; results
-    equal the chains run alone, bit for bit."""
+    """Chains of one shape share launches (grains, cubic anisotropy, DMI,
+    adaptive cone, demag once per sweep); a temperature or anisotropy change
+    in one of them regroups; results equal the chains run alone, bit for bit."""
     grid, cell = (40, 24, 2), (4e-9, 4e-9, 3e-9)
     N = int(np.prod(grid))
     gid, ng = workloads.voronoi_grains(grid, cell, seed=3, spacing=12e-9)
     ea, K1, K2, Tc = workloads.grain_properties(ng, seed=4)
 
-    def make(i, grains):
+    cub_axes = np.array([[1.0, 1.0, 0.0], [-1.0, 1.0, 0.3]])
+
+    def make(i, grains, cub):
         c = pkg.Chain(grid, cell, T=300.0 + 40.0 * i, B=(0.0, 0.01 * i, 0.1 - 0.05 * i), D0=1e-3, demag=True,
                       refresh_per_sweep=1, seed=11 + i, chain_id=i, adapt_every=3, init=1, **MAT)
         if grains:
             c.set_grains(gid, ea, K1, K2, Tc, 0.1)
+        if cub:
+            c.set_anisotropy("cubic", cub_axes, 3e5, -5e4, me_scaling=True)
         return c
-    kinds = [False, False, True, False, True]
-    a = [make(i, g) for i, g in enumerate(kinds)]
-    b = [make(i, g) for i, g in enumerate(kinds)]
+    # (grains, cubic anisotropy): cubic chains form groups of their own
+    kinds = [(False, False), (False, True), (True, False), (False, False), (True, True), (False, True)]
+    a = [make(i, *k) for i, k in enumerate(kinds)]
+    b = [make(i, *k) for i, k in enumerate(kinds)]
     batch = pkg.Batch(a)
     batch.sweep(5)
     batch.sync()
     a[3].set_temperature(610.0)
+    a[0].set_anisotropy("cubic", cub_axes, 2e5, 0.0)
     batch.sweep(4)
     batch.sync()
     for c in b:
         c.sweep(5)
     b[3].set_temperature(610.0)
+    b[0].set_anisotropy("cubic", cub_axes, 2e5, 0.0)
     for c in b:
         c.sweep(4)
     for ca, cb in zip(a, b):
