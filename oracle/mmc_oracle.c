@@ -16,6 +16,8 @@
  *   or_demag_*         FFT path == brute-force direct sum
  *   or_delta_F         equals E_total(after) - E_total(before) per term
  *   or_subsweep/or_run macrospin quadrature of the paper's Eq. 1 target
+ *   or_serial_*        demag off: identical to the parallel sweep; kept field ==
+ *                      direct sum; energy change == sum of accepted dF
  *   or_energy          isotropy + closed forms on uniform states (uniaxial and
  *                      the cubic <100>, <110>, <111> values), cubic symmetry
  */
@@ -579,6 +581,35 @@ static void philox_cell(const or_sys* s, int64_t p, uint64_t sweep, int tag, int
     for (int k = 0; k < 4; ++k) u[k] = or_u01(o[k]);
 }
 
+/* Steps 1-2 of a move at cell p with uniforms u: rotation uniform on the cap
+ * of 1 - cos(theta_c) = omc about the current direction, then the length
+ * change.  Writes the proposal mB and ln(f) of the length factor f. */
+static void propose(const or_sys* s, const or_class* c, const double* m, int64_t N, int64_t p, const double u[4],
+                    double omc, double mB[3], double* lnf_out) {
+    double mA[3] = {m[p], m[N + p], m[2 * N + p]};
+    double len = sqrt(mA[0] * mA[0] + mA[1] * mA[1] + mA[2] * mA[2]);
+    double n[3] = {mA[0] / len, mA[1] / len, mA[2] / len};
+    /* 1) rotation: uniform on the cap of half-angle theta_c about n */
+    double t = u[0] * omc;               /* 1 - cos(theta) */
+    double ct = 1.0 - t, st = sqrt(t * (2.0 - t));
+    double phi = 2.0 * M_PI * u[1];
+    /* orthonormal frame of n: Duff et al., JCGT 6(1), 2017 */
+    double sg = copysign(1.0, n[2]);
+    double a = -1.0 / (sg + n[2]);
+    double b = n[0] * n[1] * a;
+    double e1[3] = {1.0 + sg * n[0] * n[0] * a, sg * b, -sg * n[0]};
+    double e2[3] = {b, sg + n[1] * n[1] * a, -n[1]};
+    double cp_ = cos(phi), sp_ = sin(phi);
+    double nb[3];
+    for (int k = 0; k < 3; ++k) nb[k] = ct * n[k] + st * (cp_ * e1[k] + sp_ * e2[k]);
+    /* 2) length change */
+    double lnf, f;
+    if (s->lenmode == 0) { f = 1.0 - c->sigma + 2.0 * c->sigma * u[2]; lnf = log(f); }
+    else { lnf = (2.0 * u[2] - 1.0) * log1p(c->sigma); f = exp(lnf); }
+    for (int k = 0; k < 3; ++k) mB[k] = f * len * nb[k];
+    *lnf_out = lnf;
+}
+
 int64_t or_subsweep(const or_sys* s, const or_class* cc, double* m, const double* h,
                     uint64_t sweep, int colour, double cone_deg,
                     int8_t* acc, double* margin, double* mB_out) {
@@ -595,29 +626,9 @@ int64_t or_subsweep(const or_sys* s, const or_class* cc, double* m, const double
             continue;
         }
         const or_class* c = &cc[cls_of(s, p)];
-        double u[4];
+        double u[4], mB[3], lnf;
         philox_cell(s, p, sweep, 0, colour, u);
-        double mA[3] = {m[p], m[N + p], m[2 * N + p]};
-        double len = sqrt(mA[0] * mA[0] + mA[1] * mA[1] + mA[2] * mA[2]);
-        double n[3] = {mA[0] / len, mA[1] / len, mA[2] / len};
-        /* 1) rotation: uniform on the cap of half-angle theta_c about n */
-        double t = u[0] * omc;               /* 1 - cos(theta) */
-        double ct = 1.0 - t, st = sqrt(t * (2.0 - t));
-        double phi = 2.0 * M_PI * u[1];
-        /* orthonormal frame of n: Duff et al., JCGT 6(1), 2017 */
-        double sg = copysign(1.0, n[2]);
-        double a = -1.0 / (sg + n[2]);
-        double b = n[0] * n[1] * a;
-        double e1[3] = {1.0 + sg * n[0] * n[0] * a, sg * b, -sg * n[0]};
-        double e2[3] = {b, sg + n[1] * n[1] * a, -n[1]};
-        double cp_ = cos(phi), sp_ = sin(phi);
-        double nb[3];
-        for (int k = 0; k < 3; ++k) nb[k] = ct * n[k] + st * (cp_ * e1[k] + sp_ * e2[k]);
-        /* 2) length change */
-        double lnf, f;
-        if (s->lenmode == 0) { f = 1.0 - c->sigma + 2.0 * c->sigma * u[2]; lnf = log(f); }
-        else { lnf = (2.0 * u[2] - 1.0) * log1p(c->sigma); f = exp(lnf); }
-        double mB[3] = {f * len * nb[0], f * len * nb[1], f * len * nb[2]};
+        propose(s, c, m, N, p, u, omc, mB, &lnf);
         if (mB_out) { mB_out[p] = mB[0]; mB_out[N + p] = mB[1]; mB_out[2 * N + p] = mB[2]; }
         /* 3) free-energy change */
         double dF[6];
@@ -630,6 +641,102 @@ int64_t or_subsweep(const or_sys* s, const or_class* cc, double* m, const double
         if (margin) margin[p] = mg;
         if (acc) acc[p] = (int8_t)ok;
         if (ok) { m[p] = mB[0]; m[N + p] = mB[1]; m[2 * N + p] = mB[2]; nacc += 1; }
+    }
+    return nacc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Serial MMC with the exact demag interaction                             */
+/* ------------------------------------------------------------------ */
+struct or_serial {
+    int nx, ny, nz;
+    double* T;     /* 6 tensor components for every offset (dx, dy, dz) in [-(n-1), n-1]^3 */
+};
+
+static const double* ser_tensor(const or_serial* q, int dx, int dy, int dz) {
+    int64_t ix = dx + q->nx - 1, iy = dy + q->ny - 1, iz = dz + q->nz - 1;
+    return &q->T[6 * ((iz * (2 * q->ny - 1) + iy) * (2 * q->nx - 1) + ix)];
+}
+
+or_serial* or_serial_create(const or_sys* s) {
+    or_serial* q = (or_serial*)calloc(1, sizeof(or_serial));
+    q->nx = s->nx; q->ny = s->ny; q->nz = s->nz;
+    int64_t n = (int64_t)(2 * s->nx - 1) * (2 * s->ny - 1) * (2 * s->nz - 1);
+    q->T = (double*)malloc(sizeof(double) * 6 * n);
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t o = 0; o < n; ++o) {
+        int dx = (int)(o % (2 * s->nx - 1)) - (s->nx - 1);
+        int dy = (int)((o / (2 * s->nx - 1)) % (2 * s->ny - 1)) - (s->ny - 1);
+        int dz = (int)(o / ((int64_t)(2 * s->nx - 1) * (2 * s->ny - 1))) - (s->nz - 1);
+        or_newell(dx * s->hx, dy * s->hy, dz * s->hz, s->hx, s->hy, s->hz, &q->T[6 * o]);
+    }
+    return q;
+}
+
+void or_serial_destroy(or_serial* q) {
+    if (!q) return;
+    free(q->T);
+    free(q);
+}
+
+/* h_j += -N(j - p) dm for every cell j: the field change of a change dm at p. */
+static void ser_field_update(const or_serial* q, int64_t N, int64_t p, const double dm[3], double* h) {
+    int nx = q->nx, ny = q->ny;
+    int px = (int)(p % nx), py = (int)((p / nx) % ny), pz = (int)(p / ((int64_t)nx * ny));
+    for (int64_t j = 0; j < N; ++j) {
+        int x = (int)(j % nx), y = (int)((j / nx) % ny), z = (int)(j / ((int64_t)nx * ny));
+        const double* t = ser_tensor(q, x - px, y - py, z - pz);   /* xx yy zz xy xz yz */
+        h[j] -= t[0] * dm[0] + t[3] * dm[1] + t[4] * dm[2];
+        h[N + j] -= t[3] * dm[0] + t[1] * dm[1] + t[5] * dm[2];
+        h[2 * N + j] -= t[4] * dm[0] + t[5] * dm[1] + t[2] * dm[2];
+    }
+}
+
+void or_serial_field(const or_serial* q, const double* m, double* h) {
+    int64_t N = (int64_t)q->nx * q->ny * q->nz;
+    for (int64_t k = 0; k < 3 * N; ++k) h[k] = 0.0;
+    for (int64_t p = 0; p < N; ++p) {
+        double mp[3] = {m[p], m[N + p], m[2 * N + p]};
+        ser_field_update(q, N, p, mp, h);
+    }
+}
+
+int64_t or_serial_sweep(const or_serial* q, const or_sys* s, const or_class* cc, double* m, double* h,
+                        uint64_t sweep, double cone_deg, int self_term, double* dE_accepted) {
+    int nx = s->nx, ny = s->ny, nz = s->nz;
+    int64_t N = (int64_t)nx * ny * nz;
+    double omc = 2.0 * pow(sin(0.5 * cone_deg * M_PI / 180.0), 2);
+    double V = s->hx * s->hy * s->hz;
+    const double* N0 = s->demag ? ser_tensor(q, 0, 0, 0) : NULL;
+    int64_t nacc = 0;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int64_t p = 0; p < N; ++p) {
+            int x = (int)(p % nx), y = (int)((p / nx) % ny), z = (int)(p / ((int64_t)nx * ny));
+            if (((x + y + z) & 1) != colour) continue;
+            int cp = cls_of(s, p);
+            double u[4], mB[3], lnf, dF[6];
+            philox_cell(s, p, sweep, 0, colour, u);
+            propose(s, &cc[cp], m, N, p, u, omc, mB, &lnf);
+            or_delta_F(s, cc, m, s->demag ? h : NULL, p, mB, dF);
+            double D[3] = {mB[0] - m[p], mB[1] - m[N + p], mB[2] - m[2 * N + p]};
+            if (s->demag && self_term) {
+                /* exact change of the total demag energy: the current-field term of
+                 * Eq. 14 plus the cell's self term (mu0 V Ms0^2 / 2) D.N(0).D */
+                double ND[3] = {N0[0] * D[0] + N0[3] * D[1] + N0[4] * D[2],
+                                N0[3] * D[0] + N0[1] * D[1] + N0[5] * D[2],
+                                N0[4] * D[0] + N0[5] * D[1] + N0[2] * D[2]};
+                double kT = OR_KB * T_of(s, cp);
+                dF[5] += 0.5 * OR_MU0 * V * s->Ms0 * s->Ms0 / kT * (D[0] * ND[0] + D[1] * ND[1] + D[2] * ND[2]);
+            }
+            double dFt = dF[0] + dF[1] + dF[2] + dF[3] + dF[4] + dF[5];
+            double k = (s->lenmode == 0) ? 4.0 : 3.0;
+            if ((k * lnf - dFt) - log(u[3]) > 0.0) {
+                m[p] = mB[0]; m[N + p] = mB[1]; m[2 * N + p] = mB[2];
+                if (s->demag) ser_field_update(q, N, p, D, h);
+                if (dE_accepted) *dE_accepted += dFt * OR_KB * T_of(s, cp);
+                nacc += 1;
+            }
+        }
     }
     return nacc;
 }

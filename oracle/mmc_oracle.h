@@ -124,6 +124,28 @@ int64_t or_subsweep(const or_sys* s, const or_class* cc, double* m, const double
                     uint64_t sweep, int colour, double cone_deg,
                     int8_t* acc, double* margin, double* mB_out);
 
+/* Serial MMC with the exact demag interaction (paper Sec. III, the comparison
+ * of the parallel algorithm with a serial one; App. B): the cells are visited
+ * one at a time (colour 0 cells in index order, then colour 1 cells), each
+ * with the same compound move and Philox numbers as in the parallel sweep;
+ * the demag field h = -N*m of every cell is kept current, updated after
+ * every accepted move.  The demag part of dF is Eq. 14's -V mu0 dM.H_d with
+ * that current field (self_term 0: the paper's serial version), or the exact
+ * change of the total demag energy, which adds the cell's self term
+ * (mu0 V Ms0^2 / 2) dm.N(0).dm (self_term 1).  With demag off a serial sweep
+ * equals the two parallel colour passes.
+ * or_serial_create tabulates the Newell tensor for every cell offset;
+ * or_serial_field fills h from m by the direct sum over that table.
+ * or_serial_sweep: one sweep, h in/out (current field of m on entry);
+ * dE_accepted (optional) accumulates the accepted dF in Joules.  Returns the
+ * number of accepted moves. */
+typedef struct or_serial or_serial;
+or_serial* or_serial_create(const or_sys* s);
+void or_serial_destroy(or_serial* q);
+void or_serial_field(const or_serial* q, const double* m, double* h);
+int64_t or_serial_sweep(const or_serial* q, const or_sys* s, const or_class* cc, double* m, double* h,
+                        uint64_t sweep, double cone_deg, int self_term, double* dE_accepted);
+
 /* Initial state: kind 0 uniform along dir, kind 1 random directions
  * (Philox tag 1).  Length = class m0. */
 void or_init_state(const or_sys* s, const or_class* cc, int kind, const double dir[3], double* m);

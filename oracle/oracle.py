@@ -73,6 +73,13 @@ def _declare(L):
     L.or_subsweep.argtypes = [C.POINTER(OrSys), C.POINTER(OrClass), _dp, _dp, C.c_uint64, C.c_int, C.c_double,
                               C.POINTER(C.c_int8), _dp, _dp]
     L.or_subsweep.restype = C.c_int64
+    L.or_serial_create.argtypes = [C.POINTER(OrSys)]
+    L.or_serial_create.restype = C.c_void_p
+    L.or_serial_destroy.argtypes = [C.c_void_p]
+    L.or_serial_field.argtypes = [C.c_void_p, _dp, _dp]
+    L.or_serial_sweep.argtypes = [C.c_void_p, C.POINTER(OrSys), C.POINTER(OrClass), _dp, _dp, C.c_uint64,
+                                  C.c_double, C.c_int, _dp]
+    L.or_serial_sweep.restype = C.c_int64
     L.or_init_state.argtypes = [C.POINTER(OrSys), C.POINTER(OrClass), C.c_int, _dp, _dp]
     L.or_run.argtypes = [C.POINTER(OrSys), C.POINTER(OrClass), C.c_void_p, _dp, C.c_uint64, C.c_int64,
                          C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int64), _dp]
@@ -273,6 +280,54 @@ class System:
         n = lib().or_subsweep(C.byref(self.s), self.cc, _ptr(m), _ptr(hb) if hb is not None else None,
                               int(sweep), int(colour), float(cone_deg), _ptr(acc, C.c_int8), _ptr(margin), _ptr(mB))
         return m, acc, margin, mB, int(n)
+
+    def serial_field(self, m):
+        """h = -N*m by the direct sum over the serial run's tensor table."""
+        m = np.ascontiguousarray(m, dtype=np.float64).reshape(3, -1)
+        h = np.zeros_like(m)
+        lib().or_serial_field(self._serial_table(), _ptr(m), _ptr(h))
+        return h
+
+    def __del__(self):
+        if getattr(self, "_ser", None) is not None:
+            lib().or_serial_destroy(self._ser)
+            self._ser = None
+
+    def _serial_table(self):
+        if getattr(self, "_ser", None) is None:
+            self._ser = lib().or_serial_create(C.byref(self.s))
+        return self._ser
+
+    def serial_run(self, m, n, sweep0=0, cone_deg=30, adapt_every=0, window=0, h=None, self_term=False):
+        """n serial sweeps with the demag field kept current, in place on m (and
+        on h, the current field, computed fresh when None); self_term: exact
+        total-energy change (adds the cell's self term to Eq. 14).  Returns
+        (series[n,5], cone_deg, window, h, accepted dF in J).  The cone rule is
+        that of run()."""
+        assert m.dtype == np.float64 and m.flags.c_contiguous
+        q = self._serial_table()
+        if h is None:
+            h = self.serial_field(m) if self.s.demag else np.zeros_like(m)
+        assert h.dtype == np.float64 and h.flags.c_contiguous
+        series = np.zeros((int(n), 5))
+        dE = C.c_double(0.0)
+        cd, win = int(cone_deg), int(window)
+        for i in range(int(n)):
+            sw = int(sweep0) + i
+            nacc = lib().or_serial_sweep(q, C.byref(self.s), self.cc, _ptr(m), _ptr(h), sw, float(cd), int(bool(self_term)),
+                                         C.byref(dE))
+            win += nacc
+            series[i, :3] = m.mean(axis=1)
+            series[i, 3] = (m * m).sum(axis=0).mean()
+            series[i, 4] = nacc
+            if adapt_every > 0 and (sw + 1) % adapt_every == 0:
+                tot = adapt_every * self.N
+                if 100 * win > 55 * tot and cd < 180:
+                    cd += 1
+                elif 100 * win < 45 * tot and cd > 1:
+                    cd -= 1
+                win = 0
+        return series, cd, win, h, dE.value
 
     def run(self, m, n, sweep0=0, cone_deg=30, adapt_every=0, window=0):
         """n full sweeps in place; returns (series[n,5], cone_deg, window)."""

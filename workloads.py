@@ -31,6 +31,14 @@ WORKLOADS = {
 
 BATCH_SIZES = [(64, 64, 1), (128, 128, 1), (256, 256, 2), (512, 512, 2)]
 
+# Switching events of a small Ni80Fe20 platelet (a scaled-down stand-in for the
+# 400x200x5 nm ellipse of the parallel-vs-serial comparison): 80x40x5 nm in
+# 5 nm cells, no crystal anisotropy (the demag interaction sets the easy axis
+# along x), 300 K, started uniform along -x with a field of 0.14 T along +x,
+# near its coercive field (median switching after ~1000 sweeps).
+SWITCHING = dict(grid=(16, 8, 1), cell=(5e-9, 5e-9, 5e-9), Ms0=8.6e5, A0=1.3e-11, K1=0.0, Tc=870.0, T=300.0,
+                 B=(0.14, 0.0, 0.0), init_dir=(-1.0, 0.0, 0.0), cone_deg=30, adapt_every=100, max_sweeps=2000)
+
 
 def random_state(N, seed, lmin=0.5, lmax=1.0):
     """(3, N) float32: isotropic directions, lengths uniform in [lmin, lmax]."""
