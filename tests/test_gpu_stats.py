@@ -76,3 +76,34 @@ def test_above_tc_granular(pkg):
     m = o.init_state("uniform")
     os_, _, _ = o.run(m, n, cone_deg=30, adapt_every=100)
     _compare(gs, os_, n // 5)
+
+
+def test_switching_statistics_gpu_vs_serial_oracle(pkg):
+    """The paper's parallel-vs-serial switching check with the GPU chain as the
+    parallel algorithm (demag refreshed once per sweep): its switching-time
+    distribution on the platelet near its coercive field matches that of the
+    oracle's serial MMC (demag field updated after every accepted move);
+    96 events each, two-sample Kolmogorov-Smirnov test."""
+    from scipy.stats import ks_2samp
+    import workloads
+    from oracle import switching
+    p = workloads.SWITCHING
+    d = np.asarray(p["B"]) / np.linalg.norm(p["B"])
+    times = []
+    for i in range(96):
+        c = pkg.Chain(p["grid"], p["cell"], Ms0=p["Ms0"], A0=p["A0"], K1=p["K1"], Tc=p["Tc"], T=p["T"], B=p["B"],
+                      demag=True, refresh_per_sweep=1, seed=3000 + i, cone_deg=p["cone_deg"],
+                      adapt_every=p["adapt_every"], init=0, init_dir=p["init_dir"])
+        t = p["max_sweeps"]
+        for sw0 in range(0, p["max_sweeps"], 100):
+            k = np.nonzero(c.sweep_record(100)[:, :3] @ d > 0)[0]
+            if len(k):
+                t = sw0 + int(k[0])
+                break
+        times.append(t)
+    gpu = np.array(times)
+    ser = switching.switch_times(p, np.arange(96) + 6000, "serial")
+    print("gpu parallel mean %.0f median %.0f; oracle serial mean %.0f median %.0f"
+          % (gpu.mean(), np.median(gpu), ser.mean(), np.median(ser)))
+    assert np.median(gpu) < 0.8 * p["max_sweeps"]
+    assert ks_2samp(gpu, ser).pvalue > 1e-3
