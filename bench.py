@@ -140,6 +140,46 @@ def batched_leg(n_chains=64, sweeps=100, seed=0):
             "speedup": t_plain / t_batch}
 
 
+def fe_film_leg(sweeps=100, warmup=5, every=10, seed=0):
+    """The granular Fe film with cubic anisotropy (paper Fig. 5 problem, at 8
+    of its 10 layers): per-cell colour pass with grain classes and the cubic
+    term, demag refreshed once per sweep as in the paper.  Cell-updates/s and
+    the HIP-event time of each kernel kind over the sampled sweeps."""
+    import torch
+    from paper_2106_05593_amd import Chain
+    p = workloads.FE_FILM
+    grid = p["grid"]
+    N = int(np.prod(grid))
+    gid, ng = workloads.voronoi_grains(grid, p["cell"], p["grain_spacing"], seed=7)
+    ch = Chain(grid, p["cell"], Ms0=p["Ms0"], A0=p["A0"], K1=0.0, Tc=p["Tc"], T=p["T"], B=p["B"], demag=True,
+               refresh_per_sweep=1, adapt_every=100, seed=seed, init=0, init_dir=p["init_dir"])
+    ch.set_grains(gid, np.tile([0.0, 0.0, 1.0], (ng, 1)), np.zeros(ng), np.zeros(ng), np.full(ng, p["Tc"]),
+                  p["bscale"])
+    ch.set_anisotropy("cubic", np.array(p["cubic_axes"]), p["K1c"], p["K2c"], me_scaling=True)
+    ch.sweep(warmup)
+    ch.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms, cnt = ch.sweep_timed(sweeps, every=every)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ch.stats()
+    assert st["sweeps"] == warmup + sweeps and np.isfinite(st["m2_mean"])
+    kern = {}
+    for k, name in enumerate(KINDS):
+        if cnt[k]:
+            avg = 1e3 * ms[k] / cnt[k]
+            b = algorithmic_bytes(grid, True, name)
+            if name == "colour_pass":
+                b += 4 * N                                # class ids: the pass's cells and the other colour's
+            kern[name] = {"launches": int(cnt[k]), "avg_us": round(avg, 3), "alg_bytes": b,
+                          "GBs": round(b / (avg * 1e-6) / 1e9, 1)}
+    ch.close()
+    return {"workload": "fe_film_400x400x8", "grid": list(grid), "cell_nm": 2, "grains": int(ng),
+            "demag_refresh_per_sweep": 1, "sweeps": sweeps, "ms_per_sweep": 1e3 * wall / sweeps,
+            "cell_updates_per_s": N * sweeps / wall, "kernels": kern}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +188,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-fe-film", action="store_true")
     ap.add_argument("--profile-every", type=int, default=10,
                     help="bracket every kernel of one timed sweep in this many with HIP events")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -221,6 +262,9 @@ def main():
     if not args.no_batched:
         print("bench: batched chains leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg()
+    if not args.no_fe_film:
+        print("bench: granular Fe film leg (cubic anisotropy)", file=sys.stderr, flush=True)
+        out["fe_film"] = fe_film_leg()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -31,6 +31,18 @@ WORKLOADS = {
 
 BATCH_SIZES = [(64, 64, 1), (128, 128, 1), (256, 256, 2), (512, 512, 2)]
 
+# Granular Fe film with cubic anisotropy (the paper's Fig. 5 problem, Sec. III):
+# Ms0 1.71 MA/m, A0 21 pJ/m, cubic K1 48 kJ/m^3 and K2 -10 kJ/m^3 with the
+# me^{l(l+1)/2} law, Tc 1044 K, 300 K, 2 nm cells, 3-D Voronoi grains of 10 nm
+# mean seed spacing that interact through the demag field only (exchange
+# across grain boundaries 0), crystal axes along x, y, z in every grain, field
+# along the in-plane cubic easy axis x.  800x800 nm in the plane as in the
+# paper; 16 nm thick (8 cells) where the paper has 20 nm (10 cells), since
+# the demag path here handles at most 8 layers; open boundaries.
+FE_FILM = dict(grid=(400, 400, 8), cell=(2e-9, 2e-9, 2e-9), Ms0=1.71e6, A0=2.1e-11, K1c=4.8e4, K2c=-1.0e4,
+               Tc=1044.0, T=300.0, B=(0.05, 0.0, 0.0), grain_spacing=10e-9, bscale=0.0,
+               cubic_axes=((1.0, 0.0, 0.0), (0.0, 1.0, 0.0)), init_dir=(1.0, 0.0, 0.0))
+
 # Switching events of a small Ni80Fe20 platelet (a scaled-down stand-in for the
 # 400x200x5 nm ellipse of the parallel-vs-serial comparison): 80x40x5 nm in
 # 5 nm cells, no crystal anisotropy (the demag interaction sets the easy axis
