@@ -156,11 +156,12 @@ def test_energy_matches_oracle(O, mmc, demag):
     assert abs(E - Eo.sum()) < 2e-6 * scale
 
 
-@pytest.mark.parametrize("with_demag", [False, True])
-def test_subsweep_decisions_temperature_profile(O, mmc, with_demag):
+@pytest.mark.parametrize("with_demag,nx", [(False, 30), (True, 30), (True, 40)])
+def test_subsweep_decisions_temperature_profile(O, mmc, with_demag, nx):
     """Non-uniform temperature profile: grains at their own temperatures
-    (below and above Tc), DMI, grain-boundary exchange scale, optional demag."""
-    grid, cell = (30, 22, 2), (4e-9, 4e-9, 3e-9)
+    (below and above Tc), DMI, grain-boundary exchange scale, optional demag;
+    rows of odd and of even slot counts."""
+    grid, cell = (nx, 22, 2), (4e-9, 4e-9, 3e-9)
     N = int(np.prod(grid))
     gid, ng = workloads.voronoi_grains(grid, cell, 9e-9, 5)
     ea, K1, K2, Tc = workloads.grain_properties(ng, seed=6)
@@ -197,15 +198,17 @@ def _rot(seed):
     return q.T            # rows: orthonormal crystal axes
 
 
-@pytest.mark.parametrize("case", ["uniform", "grains_profile_demag"])
-def test_subsweep_decisions_cubic(O, mmc, case):
+@pytest.mark.parametrize("case,nx", [("uniform", 34), ("grains_profile_demag", 34), ("uniform", 32),
+                                     ("grains_profile_demag", 40)])
+def test_subsweep_decisions_cubic(O, mmc, case, nx):
     """Cubic anisotropy (Eq. 12) with the me^{l(l+1)/2} law: one crystal for
     every cell (with DMI), or one per grain at per-grain temperatures with
     demag.  Constants are large (V K1/kT ~ 3, V K2/kT ~ 10), the exchange is
     weak and every length sits at its grain's m0, so the cubic term decides
     many moves (on the oracle, dropping it changes 20-90 of ~900 decisions
-    per pass for the single crystal and 2-20 with grains and demag)."""
-    grid, cell = (34, 26, 2), (3e-9, 3e-9, 3e-9)
+    per pass for the single crystal and 2-20 with grains and demag); rows of
+    odd and of even slot counts."""
+    grid, cell = (nx, 26, 2), (3e-9, 3e-9, 3e-9)
     N = int(np.prod(grid))
     kw = dict(Ms0=1.71e6, A0=2e-12, K1=0.0, Tc=1044.0, T=300.0, B=(0.05, 0.0, 0.02), seed=17, chain_id=3)
     demag = case.endswith("demag")
