@@ -128,7 +128,8 @@ def test_subsweep_decisions_with_demag_field(O, mmc):
                                        ((13, 6, 3), (4e-9, 4e-9, 2e-9)), ((33, 17, 4), (3e-9, 5e-9, 2e-9)),
                                        ((64, 64, 8), (3e-9,) * 3), ((256, 256, 1), (4e-9, 4e-9, 2e-9)),
                                        ((48, 300, 2), (5e-9, 4e-9, 3e-9)), ((64, 520, 4), (5e-9,) * 3),
-                                       ((40, 150, 8), (3e-9,) * 3), ((24, 200, 6), (4e-9, 3e-9, 2e-9))])
+                                       ((40, 150, 8), (3e-9,) * 3), ((24, 200, 6), (4e-9, 3e-9, 2e-9)),
+                                       ((16, 300, 8), (2e-9,) * 3), ((20, 270, 6), (3e-9, 3e-9, 2e-9))])
 def test_demag_field_matches_oracle(O, mmc, grid, cell):
     N = int(np.prod(grid))
     ch = mmc.Chain(grid, cell, T=300.0, demag=True, **MAT)
