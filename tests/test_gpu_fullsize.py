@@ -1,5 +1,6 @@
 """Parity at the full benchmark size (1024 x 1024 x 4 cells of 5 nm, demag on),
-through the C-ABI, in the launch configuration the benchmark times.
+through the C-ABI, in the launch configuration the benchmark times, and at
+the full size of its granular Fe film leg.
 
 * demag field: sampled cells against the oracle's direct sum over all 4.2 M
   source cells (relative error per sampled vector <= 1e-5 of the field scale);
@@ -68,3 +69,45 @@ def test_colour_pass_whole_grid(chain):
         print("colour %d: %d cells, %d accepted, %d mismatches, worst |margin| %.2e"
               % (colour, mine.sum(), (acc_o == 1).sum(), mism.sum(), worst))
         assert worst < 2e-4
+
+
+def test_fe_film_colour_pass_whole_grid():
+    """The granular Fe film of the benchmark's second leg at its full size
+    (400 x 400 x 8 cells of 2 nm, 10k Voronoi grains coupled by demag only,
+    cubic anisotropy with the me^{l(l+1)/2} law), the colour-pass kernel it
+    times: whole-grid decisions against the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_2106_05593_amd import Chain
+    p = workloads.FE_FILM
+    grid, cell = p["grid"], p["cell"]
+    N = int(np.prod(grid))
+    gid, ng = workloads.voronoi_grains(grid, cell, p["grain_spacing"], seed=7)
+    kw = dict(Ms0=p["Ms0"], A0=p["A0"], Tc=p["Tc"], T=p["T"], B=p["B"], demag=True, seed=5)
+    ch = Chain(grid, cell, K1=0.0, **kw)
+    ea = np.tile([0.0, 0.0, 1.0], (ng, 1))
+    ch.set_grains(gid, ea, np.zeros(ng), np.zeros(ng), np.full(ng, p["Tc"]), p["bscale"])
+    ax = np.array(p["cubic_axes"])
+    ch.set_anisotropy("cubic", ax, p["K1c"], p["K2c"], me_scaling=True)
+    R = np.stack([ax[0], ax[1], np.cross(ax[0], ax[1])])
+    ref = O.System(grid, cell, K1=0.0, cls=gid, ea=ea, K1s=np.full(ng, p["K1c"]), K2s=np.full(ng, p["K2c"]),
+                   Tcs=np.full(ng, p["Tc"]), bscale=p["bscale"], cubic_axes=R, kscale=True, **kw)
+    c = ref.coeffs()
+    m = workloads.perturbed_uniform_state(N, seed=4, L=c["me"], spread=0.4, axis=(1.0, 0.0, 0.0))
+    x = np.arange(N) % grid[0]
+    h = np.stack([-0.2 + 0.05 * np.sin(2 * np.pi * x / grid[0]), 0.03 * np.cos(2 * np.pi * x / 53.0),
+                  -0.1 * np.ones(N)]).astype(np.float32)
+    for colour, sweep in ((0, 31), (1, 90001)):
+        ch.set_m(m)
+        ch.set_state(sweep, 25, 0)
+        acc = ch.subsweep(colour, torch.from_numpy(h).cuda()).cpu().numpy().astype(np.int16)
+        _, acc_o, margin, _, _ = ref.subsweep(m.astype(np.float64), sweep, colour, 25.0, h=h.astype(np.float64))
+        mine = acc_o >= 0
+        assert np.array_equal(acc == 255, ~mine)
+        mism = mine & (acc != acc_o)
+        worst = np.abs(margin[mism]).max() if mism.any() else 0.0
+        print("colour %d: %d cells, %d accepted, %d mismatches, worst |margin| %.2e"
+              % (colour, mine.sum(), (acc_o == 1).sum(), mism.sum(), worst))
+        assert worst < 2e-4
+    ch.close()
