@@ -180,6 +180,40 @@ def fe_film_leg(sweeps=100, warmup=5, every=10, seed=0):
             "cell_updates_per_s": N * sweeps / wall, "kernels": kern}
 
 
+def profile_leg(sweeps=50, warmup=5, every=10, seed=0):
+    """The benchmark grid under a Gaussian in-plane temperature profile (paper
+    Sec. IV, laser heating): 16 temperature classes from 0.9 Tc at the rim to
+    1.1 Tc at the centre (FWHM-like width 2 um), each cell's move judged at
+    its class's temperature; per-cell colour pass with class ids."""
+    import torch
+    from paper_2106_05593_amd import Chain
+    wl = workloads.WORKLOADS["loop_1024x1024x4"]
+    mat = workloads.BASE_MATERIAL
+    grid = wl["grid"]
+    N = int(np.prod(grid))
+    cls, T_of = workloads.gaussian_temperature_classes(grid, wl["cell"], 2e-6, 1.1 * mat["Tc"], 0.9 * mat["Tc"], 16)
+    n = len(T_of)
+    ch = Chain(grid, wl["cell"], Ms0=mat["Ms0"], A0=mat["A0"], K1=mat["K1"], Tc=mat["Tc"], T=wl["T"], B=wl["B"],
+               mf=mat["mf"], mu=mat["mu"], demag=True, adapt_every=wl["adapt_every"], seed=seed, init=0)
+    ch.set_grains(cls, np.tile(mat["easy_axis"], (n, 1)), np.full(n, mat["K1"]), np.zeros(n), np.full(n, mat["Tc"]),
+                  1.0)
+    ch.set_grain_temperatures(T_of)
+    ch.sweep(warmup)
+    ch.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms, cnt = ch.sweep_timed(sweeps, every=every)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert np.isfinite(ch.stats()["m2_mean"])
+    kern = {name: {"launches": int(cnt[k]), "avg_us": round(1e3 * ms[k] / cnt[k], 3)}
+            for k, name in enumerate(KINDS) if cnt[k]}
+    ch.close()
+    return {"workload": "loop_1024x1024x4 + Gaussian temperature profile (16 classes, 0.9-1.1 Tc)",
+            "sweeps": sweeps, "ms_per_sweep": 1e3 * wall / sweeps, "cell_updates_per_s": N * sweeps / wall,
+            "kernels": kern}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +223,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fe-film", action="store_true")
+    ap.add_argument("--no-profile-leg", action="store_true")
     ap.add_argument("--profile-every", type=int, default=10,
                     help="bracket every kernel of one timed sweep in this many with HIP events")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -265,6 +300,9 @@ def main():
     if not args.no_fe_film:
         print("bench: granular Fe film leg (cubic anisotropy)", file=sys.stderr, flush=True)
         out["fe_film"] = fe_film_leg()
+    if not args.no_profile_leg:
+        print("bench: temperature-profile leg", file=sys.stderr, flush=True)
+        out["temperature_profile"] = profile_leg()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
