@@ -169,11 +169,17 @@ class Chain:
         return self._h
 
     def set_grains(self, grain_of_cell, easy_axes, K1, K2, Tc, boundary_exchange_scale):
-        gid = np.ascontiguousarray(grain_of_cell, dtype=np.uint32)
+        """Per-cell grain ids (N, natural order) and per-grain easy axis (n, 3),
+        K1, K2, Tc (n,); returns the anisotropy to the uniaxial form and clears
+        grain temperatures."""
+        gid = np.ascontiguousarray(grain_of_cell, dtype=np.uint32).reshape(-1)
         ea = np.ascontiguousarray(easy_axes, dtype=np.float64).reshape(-1)
-        k1 = np.ascontiguousarray(K1, dtype=np.float64)
-        k2 = np.ascontiguousarray(K2, dtype=np.float64)
-        tc = np.ascontiguousarray(Tc, dtype=np.float64)
+        k1 = np.ascontiguousarray(K1, dtype=np.float64).reshape(-1)
+        k2 = np.ascontiguousarray(K2, dtype=np.float64).reshape(-1)
+        tc = np.ascontiguousarray(Tc, dtype=np.float64).reshape(-1)
+        n = tc.size
+        if gid.size != self.N or ea.size != 3 * n or k1.size != n or k2.size != n:
+            raise ValueError("need N grain ids and n easy axes (n, 3), K1, K2, Tc (n,)")
         _check(lib().mmc_set_grains(self._h, gid.ctypes.data, len(tc), ea.ctypes.data, k1.ctypes.data,
                                     k2.ctypes.data, tc.ctypes.data, float(boundary_exchange_scale)))
 
@@ -200,7 +206,10 @@ class Chain:
             return
         if kind != "cubic":
             raise ValueError("kind must be 'uniaxial' or 'cubic'")
-        ax = np.ascontiguousarray(axes, dtype=np.float64).reshape(-1, 6)
+        ax = np.ascontiguousarray(axes, dtype=np.float64)
+        if ax.size % 6 != 0 or ax.shape[-2:] != (2, 3):
+            raise ValueError("axes must be (2, 3) or (n, 2, 3)")
+        ax = ax.reshape(-1, 6)
         n = ax.shape[0]
         k1 = np.ascontiguousarray(np.broadcast_to(np.asarray(K1, dtype=np.float64), (n,)))
         k2 = np.ascontiguousarray(np.broadcast_to(np.asarray(K2, dtype=np.float64), (n,)))

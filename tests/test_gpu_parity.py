@@ -200,7 +200,7 @@ def _rot(seed):
 
 
 @pytest.mark.parametrize("case,nx", [("uniform", 34), ("grains_profile_demag", 34), ("uniform", 32),
-                                     ("grains_profile_demag", 40)])
+                                     ("grains_profile_demag", 40), ("uniform_exact", 32)])
 def test_subsweep_decisions_cubic(O, mmc, case, nx):
     """Cubic anisotropy (Eq. 12) with the me^{l(l+1)/2} law: one crystal for
     every cell (with DMI), or one per grain at per-grain temperatures with
@@ -213,12 +213,13 @@ def test_subsweep_decisions_cubic(O, mmc, case, nx):
     N = int(np.prod(grid))
     kw = dict(Ms0=1.71e6, A0=2e-12, K1=0.0, Tc=1044.0, T=300.0, B=(0.05, 0.0, 0.02), seed=17, chain_id=3)
     demag = case.endswith("demag")
-    if case == "uniform":
+    if case.startswith("uniform"):
         kw["D0"] = 1.0e-3
         R = _rot(1)
-        ch = mmc.Chain(grid, cell, demag=False, **kw)
+        lm = 1 if case.endswith("exact") else 0        # length move: paper's or exact (log-uniform)
+        ch = mmc.Chain(grid, cell, demag=False, lenmove=lm, **kw)
         ch.set_anisotropy("cubic", R[:2], 5e5, -2e6, me_scaling=True)
-        ref = O.System(grid, cell, demag=False, cubic_axes=R, kscale=True, **dict(kw, K1=5e5, K2=-2e6))
+        ref = O.System(grid, cell, demag=False, cubic_axes=R, kscale=True, lenmode=lm, **dict(kw, K1=5e5, K2=-2e6))
         L = np.full(N, ref.coeffs()["m0"])
     else:
         gid, ng = workloads.voronoi_grains(grid, cell, 9e-9, 8)
