@@ -225,6 +225,14 @@ mmc_status mmc_get_stats(mmc_ctx* ctx, mmc_stats* out);
 
 /* Run state for checkpoint/resume: with the state m this restores a chain
  * bit-exactly (the generator is stateless). */
+/* Running averages for averaging over chunks of sweeps (the hysteresis-loop
+ * rule of Sec. III: chunk averages of the magnetization): every sweep adds
+ * its <mx>, <my>, <mz>, <|m|^2> (FP64 means of the sweep's end state) to
+ * device accumulators, in batches too.  This call synchronises the context's
+ * stream (call mmc_batch_sync first for a chain in a batch), returns the
+ * averages over the sweeps since the previous call (zeros when n_out = 0) and
+ * their count, and resets the accumulators. */
+mmc_status mmc_take_averages(mmc_ctx* ctx, double avg_out[4], uint64_t* n_out);
 mmc_status mmc_get_state(mmc_ctx* ctx, uint64_t* sweep, int32_t* cone_deg, uint64_t* accepts_window);
 mmc_status mmc_set_state(mmc_ctx* ctx, uint64_t sweep, int32_t cone_deg, uint64_t accepts_window);
 

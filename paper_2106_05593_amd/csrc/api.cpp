@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -666,6 +667,23 @@ mmc_status mmc_get_stats(mmc_ctx* ctx, mmc_stats* out) {
     for (int k = 0; k < 3; ++k) out->m_mean[k] = hs.last[k];
     out->m2_mean = hs.last[3];
     out->accepts_last = hs.accepts_last;
+    return MMC_OK;
+}
+
+mmc_status mmc_take_averages(mmc_ctx* ctx, double avg_out[4], uint64_t* n_out) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!avg_out || !n_out) return fail(MMC_ERR_ARG, "NULL output");
+    DevState hs{};
+    HIPCK(hipMemcpyAsync(&hs, ctx->d_st, sizeof hs, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 4; ++k) avg_out[k] = hs.avg_n ? hs.avg_sum[k] / (double)hs.avg_n : 0.0;
+    *n_out = hs.avg_n;
+    // reset only the accumulators (the rest of the state is left as the device has it)
+    const double zsum[4] = {0.0, 0.0, 0.0, 0.0};
+    const unsigned long long zn = 0;
+    HIPCK(hipMemcpy((char*)ctx->d_st + offsetof(DevState, avg_sum), zsum, sizeof zsum, hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy((char*)ctx->d_st + offsetof(DevState, avg_n), &zn, sizeof zn, hipMemcpyHostToDevice));
     return MMC_OK;
 }
 

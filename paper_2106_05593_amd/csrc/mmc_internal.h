@@ -53,6 +53,9 @@ struct DevState {
     float omc;                       // 1 - cos(cone)
     int pad;
     double last[4];                  // <mx>, <my>, <mz>, <|m|^2> after the last sweep
+    double avg_sum[4];               // sums of those means over the sweeps since the last read-and-reset
+    unsigned long long avg_n;        // sweeps in avg_sum
+    unsigned long long pad2;
 };
 
 // Per-sweep statistics accumulators.  Blocks add fixed-point sums (scale

@@ -152,7 +152,13 @@ __global__ __launch_bounds__(kAccBins) void k_end_sweep(ChainDesc d0, const Chai
     for (int k = 0; k < 4; ++k) t[k] = ldexp((double)tot[k], -shift);
     const unsigned long long tc = (unsigned long long)tot[4];
     const double inv = 1.0 / (double)N;
-    for (int k = 0; k < 4; ++k) st->last[k] = t[k] * inv;
+    for (int k = 0; k < 4; ++k) {
+#pragma clang fp contract(off)
+        const double mk = t[k] * inv;   // the rounded mean (no fused multiply-add into the running sum)
+        st->last[k] = mk;
+        st->avg_sum[k] += mk;
+    }
+    st->avg_n += 1;
     st->accepts_last = tc;
     st->window += tc;
     const unsigned long long sw = st->sweep;

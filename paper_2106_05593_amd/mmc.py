@@ -77,6 +77,7 @@ _SIGS = {
     "mmc_demag_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_subsweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mmc_get_stats": (C.c_int, [C.c_void_p, C.POINTER(mmc_stats)]),
+    "mmc_take_averages": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "mmc_get_state": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
     "mmc_set_state": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint64]),
     "mmc_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
@@ -196,6 +197,14 @@ class Chain:
             return
         t = np.ascontiguousarray(T_of_grain, dtype=np.float64)
         _check(lib().mmc_set_grain_temperatures(self._h, t.ctypes.data, int(t.size)))
+
+    def take_averages(self):
+        """(averages of <mx>, <my>, <mz>, <|m|^2> over the sweeps since the last
+        call, number of those sweeps); resets the device accumulators."""
+        avg = (C.c_double * 4)()
+        n = C.c_uint64()
+        _check(lib().mmc_take_averages(self._h, avg, C.byref(n)))
+        return np.array(avg[:]), int(n.value)
 
     def set_anisotropy(self, kind="uniaxial", axes=None, K1=None, K2=None, me_scaling=False):
         """Anisotropy form: "uniaxial" (material / grain constants) or "cubic" with

@@ -90,3 +90,83 @@ def test_loop_gpu_matches_oracle(oracle_mod):
     far = [0, 1, 4]
     assert np.abs(gpu["m_inc"][far] - ora["m_inc"][far]).max() < 0.1
     assert gpu["m_inc"][0] < -0.7 and gpu["m_inc"][-1] > 0.7
+
+
+class ScriptedBatch:
+    """Batch stand-in: each sweep(n) call is one chunk for every chain."""
+
+    def __init__(self, chains):
+        self.chains = chains
+
+    def sweep(self, n):
+        for c in self.chains:
+            c.pending += 1
+
+    def sync(self):
+        pass
+
+
+class ScriptedAvg:
+    """Chain stand-in for the batched driver: the k-th chunk at a field has the
+    scripted average <m_z>."""
+
+    def __init__(self, script):
+        self.script, self.B, self.pending, self.k = script, None, 0, 0
+
+    def set_field(self, B):
+        self.B, self.k = B, 0
+
+    def take_averages(self):
+        if self.pending == 0:
+            return np.zeros(4), 0
+        seq = self.script[round(self.B[2], 6)]
+        v = seq[min(self.k, len(seq) - 1)]
+        self.k += 1
+        self.pending = 0
+        return np.array([0.0, 0.0, v, v * v]), 5
+
+
+def test_batched_loops_chunk_rule():
+    a = ScriptedAvg({0.0: [0.5, 0.502], 1.0: [0.9, 0.95, 0.951]})
+    b = ScriptedAvg({0.0: [0.1, 0.3, 0.4, 0.405], 1.0: [0.96, 0.961]})
+    out = hy.hysteresis_loops(ScriptedBatch([a, b]), [a, b], [0.0, 1.0], chunk=5, tol=0.01, max_chunks=6)
+    assert list(out[0]["chunks"]) == [2, 3] and list(out[1]["chunks"]) == [4, 2]
+    assert np.allclose(out[0]["m_inc"], [0.502, 0.951]) and np.allclose(out[1]["m_inc"], [0.405, 0.961])
+    assert all(o["converged"].all() for o in out)
+    assert np.allclose(out[1]["m_dec"], [-0.405, -0.961])
+
+
+@pytest.mark.gpu
+def test_running_averages_and_batched_loops():
+    """On-device running averages equal the mean of the recorded per-sweep
+    series; loops of three chains run as one batch give, at the first field,
+    the same loop points and chunk counts as each chain run alone, and
+    saturate at both ends."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2106_05593_amd as pkg
+
+    def make(i):
+        return pkg.Chain((6, 6, 1), (5e-9,) * 3, T=450.0 + 50.0 * i, seed=4 + i, chain_id=i, adapt_every=10,
+                         cone_deg=30, init=0, init_dir=(0.0, 0.0, -1.0), **MAT)
+    a, b = make(0), make(0)
+    s = a.sweep_record(37)
+    b.sweep(37)
+    avg, n = b.take_averages()
+    ref = [0.0] * 4
+    for row in s:                                   # sequential sums, as on the device
+        for k in range(4):
+            ref[k] += row[k]
+    assert n == 37 and np.array_equal(avg, np.array(ref) / 37)
+    assert b.take_averages()[1] == 0                 # reset by the read
+    alone = [hy.hysteresis_loop(make(i), FIELDS[:1], chunk=60, tol=0.02, max_chunks=6) for i in range(3)]
+    chains = [make(i) for i in range(3)]
+    batch = pkg.Batch(chains)
+    out = hy.hysteresis_loops(batch, chains, FIELDS, chunk=60, tol=0.02, max_chunks=6)
+    batch.close()
+    for o, r in zip(out, alone):
+        print("batched", o["m_inc"], o["chunks"], "alone (first field)", r["m_inc"], r["chunks"])
+        assert o["chunks"][0] == r["chunks"][0]
+        assert abs(o["m_inc"][0] - r["m_inc"][0]) < 1e-12
+        assert o["m_inc"][0] < -0.55 and o["m_inc"][-1] > 0.55
