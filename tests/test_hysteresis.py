@@ -170,3 +170,25 @@ def test_running_averages_and_batched_loops():
         assert o["chunks"][0] == r["chunks"][0]
         assert abs(o["m_inc"][0] - r["m_inc"][0]) < 1e-12
         assert o["m_inc"][0] < -0.55 and o["m_inc"][-1] > 0.55
+
+
+@pytest.mark.gpu
+def test_inverse_symmetry_against_the_simulated_decreasing_branch():
+    """The decreasing branch simulated directly (from +z saturation, fields
+    decreasing) matches the inverse-symmetry completion -m_inc(-H) of the
+    increasing branch away from the switching field (Sec. III)."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2106_05593_amd as pkg
+
+    def make(sign, seed):
+        return pkg.Chain((6, 6, 1), (5e-9,) * 3, T=500.0, seed=seed, adapt_every=10, cone_deg=30, init=0,
+                         init_dir=(0.0, 0.0, sign), **MAT)
+    inc = hy.hysteresis_loop(make(-1.0, 4), FIELDS, chunk=60, tol=0.02, max_chunks=6)
+    ch = make(1.0, 9)
+    dec = {B: hy.field_step(ch, B, (0.0, 0.0, 1.0), chunk=60, tol=0.02, max_chunks=6)[0] for B in FIELDS[::-1]}
+    print("completed", dict(zip(inc["H_dec"], inc["m_dec"])), "simulated", dec)
+    for B in (1.0, 0.3, -1.0):
+        i = list(inc["H_dec"]).index(B)
+        assert abs(dec[B] - inc["m_dec"][i]) < 0.1, B
