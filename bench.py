@@ -183,7 +183,7 @@ def fe_film_leg(sweeps=100, warmup=5, every=10, seed=0):
 def profile_leg(sweeps=50, warmup=5, every=10, seed=0):
     """The benchmark grid under a Gaussian in-plane temperature profile (paper
     Sec. IV, laser heating): 16 temperature classes from 0.9 Tc at the rim to
-    1.1 Tc at the centre (FWHM-like width 2 um), each cell's move judged at
+    1.1 Tc at the centre (2 um between the 1/e points), each cell's move judged at
     its class's temperature; per-cell colour pass with class ids."""
     import torch
     from paper_2106_05593_amd import Chain
@@ -230,7 +230,7 @@ def main():
                     help="only run a plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -62,7 +62,7 @@ typedef enum {
     MMC_ERR_OOM = -3,          /* host or device allocation failed */
     MMC_ERR_DEVICE = -4,       /* HIP runtime or kernel error */
     MMC_ERR_STATE = -5,        /* call not valid in the current state */
-    MMC_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
+    MMC_ERR_UNSUPPORTED = -6   /* valid request the library does not implement */
 } mmc_status;
 
 typedef struct { int32_t nx, ny, nz; } mmc_grid;          /* each >= 1; nx, ny <= 2048; N <= 2^28; nz <= 8 with demag */
