@@ -56,8 +56,8 @@ def test_batch_equals_sequential(pkg):
 
 
 def test_batch_shape_groups_equal_sequential(pkg):
-    """Chains of one shape share launches (grains, cubic anisotropy, DMI,
-    adaptive cone, demag once per sweep); a temperature or anisotropy change
+    """Chains of one shape share launches (grains, grain temperatures, cubic
+    anisotropy, DMI, adaptive cone, demag once per sweep); a temperature or anisotropy change
     in one of them regroups; results equal the chains run alone, bit for bit."""
     grid, cell = (40, 24, 2), (4e-9, 4e-9, 3e-9)
     N = int(np.prod(grid))
@@ -71,6 +71,8 @@ def test_batch_shape_groups_equal_sequential(pkg):
                       refresh_per_sweep=1, seed=11 + i, chain_id=i, adapt_every=3, init=1, **MAT)
         if grains:
             c.set_grains(gid, ea, K1, K2, Tc, 0.1)
+            if i == 2:                   # a temperature gradient across the grains of one chain
+                c.set_grain_temperatures(np.linspace(250.0, 750.0, ng))
         if cub:
             c.set_anisotropy("cubic", cub_axes, 3e5, -5e4, me_scaling=True)
         return c
