@@ -107,3 +107,32 @@ def test_switching_statistics_gpu_vs_serial_oracle(pkg):
           % (gpu.mean(), np.median(gpu), ser.mean(), np.median(ser)))
     assert np.median(gpu) < 0.8 * p["max_sweeps"]
     assert ks_2samp(gpu, ser).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("ka1,ka2", [(4.0, -0.8), (0.0, 60.0)])
+def test_macrospin_cubic_gpu(pkg, ka1, ka2):
+    """Independent cells (no exchange, no demag) with cubic anisotropy in the
+    exact length mode sample exp(-F_cubic/kT) over directions: the GPU chain's
+    <a^4 + b^4 + g^4> and <a^2 b^2 g^2> along the crystal axes against 2-D
+    quadrature over the sphere (the oracle's pin, now on the GPU path)."""
+    from test_oracle_cubic import _rot, _sphere_quadrature
+    T, h = 300.0, 5e-9
+    V, kT = h ** 3, 1.380649e-23 * T
+    R = _rot(5)
+    c = pkg.Chain((64, 64, 1), (h,) * 3, Ms0=1.71e6, A0=0.0, K1=0.0, Tc=1044.0, T=T, lenmove=1, seed=41, init=1,
+                  adapt_every=100, cone_deg=30)
+    c.set_anisotropy("cubic", R[:2], ka1 * kT / V, ka2 * kT / V)
+    c.sweep(600)
+    s4, s6 = [], []
+    for _ in range(80):
+        c.sweep(10)
+        m = c.get_m().astype(np.float64)
+        n = R @ (m / np.linalg.norm(m, axis=0))
+        s4.append((n ** 4).sum(axis=0).mean())
+        s6.append((n[0] ** 2 * n[1] ** 2 * n[2] ** 2).mean())
+    q4, q6 = _sphere_quadrature(ka1, ka2)
+    v4, e4 = batch_mean_se(np.array(s4), nb=10)
+    v6, e6 = batch_mean_se(np.array(s6), nb=10)
+    print("gpu <sum a^4> %.5f +- %.1e (quadrature %.5f); <a2b2g2> %.6f +- %.1e (%.6f)" % (v4, e4, q4, v6, e6, q6))
+    assert abs(v4 - q4) < 4 * e4 + 1e-3
+    assert abs(v6 - q6) < 4 * e6 + 2e-4
