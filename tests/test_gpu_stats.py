@@ -136,3 +136,36 @@ def test_macrospin_cubic_gpu(pkg, ka1, ka2):
     print("gpu <sum a^4> %.5f +- %.1e (quadrature %.5f); <a2b2g2> %.6f +- %.1e (%.6f)" % (v4, e4, q4, v6, e6, q6))
     assert abs(v4 - q4) < 4 * e4 + 1e-3
     assert abs(v6 - q6) < 4 * e6 + 2e-4
+
+
+def test_macrospins_at_their_own_temperatures_gpu(pkg):
+    """Temperature profile on the GPU path: independent cells of two classes
+    held at 0.6 Tc and 1.05 Tc (exact length mode) each sample Eq. 1 at their
+    own temperature: <m_z> and <|m|^2> per class against the single-temperature
+    quadrature that pins the oracle."""
+    from oracle import oracle as O
+    from test_oracle_sampler import quadrature
+    Tc, Bz, K1 = 700.0, 0.1, 5e4
+    temps = np.array([0.6 * Tc, 1.05 * Tc])
+    N = 64 * 64
+    cls = (np.arange(N) % 2).astype(np.uint32)
+    c = pkg.Chain((64, 64, 1), (5e-9,) * 3, Ms0=1e6, A0=0.0, K1=K1, Tc=Tc, T=temps[0], B=(0, 0, Bz), lenmove=1,
+                  sigma_fixed=0.25, seed=23, init=0)
+    c.set_grains(cls, np.tile([0.0, 0.0, 1.0], (2, 1)), np.full(2, K1), np.zeros(2), np.full(2, Tc), 1.0)
+    c.set_grain_temperatures(temps)
+    # sigma = 0.25 keeps the cone small below Tc, so directions relax slowly: long burn-in, spaced snapshots
+    c.sweep(5000)
+    snaps = []
+    for _ in range(80):
+        c.sweep(50)
+        snaps.append(c.get_m().astype(np.float64))
+    snaps = np.array(snaps)
+    for k, T in enumerate(temps):
+        ref = O.System((4, 4, 1), (5e-9,) * 3, Ms0=1e6, A0=0.0, K1=K1, Tc=Tc, T=T, B=(0, 0, Bz))
+        mz_q, m2_q = quadrature(ref, K1, Bz)
+        sel = snaps[:, :, cls == k]
+        mz, se_mz = batch_mean_se(sel[:, 2, :].mean(axis=1), nb=10)
+        m2, se_m2 = batch_mean_se((sel ** 2).sum(axis=1).mean(axis=1), nb=10)
+        print("T %.0f: <mz> %.5f +- %.1e (quadrature %.5f); <m2> %.5f +- %.1e (%.5f)" % (T, mz, se_mz, mz_q, m2, se_m2, m2_q))
+        assert abs(mz - mz_q) < 4 * se_mz + 2e-3
+        assert abs(m2 - m2_q) < 4 * se_m2 + 2e-3
