@@ -45,3 +45,15 @@ def test_status_strings_and_arg_errors():
                         ctypes.byref(h)) == mmc.MMC_ERR_ARG
     assert L.mmc_sweep(None, 1) == mmc.MMC_ERR_ARG
     assert L.mmc_batch_create(None, 0, ctypes.byref(h)) == mmc.MMC_ERR_ARG
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No CPU fallback: without the built library every call raises."""
+    import pytest
+    from paper_2106_05593_amd import mmc
+    monkeypatch.setattr(mmc, "SO", os.path.join(ROOT, "no_such_dir", "libmmc.so"))
+    monkeypatch.setattr(mmc, "_lib", None)
+    with pytest.raises(ImportError):
+        mmc.lib()
+    with pytest.raises(ImportError):
+        mmc.Chain((4, 4, 1), (5e-9,) * 3, Ms0=1e6, A0=1e-11, K1=0.0, Tc=700.0, T=300.0)
