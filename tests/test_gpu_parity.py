@@ -266,3 +266,24 @@ def test_set_anisotropy_errors(mmc):
         ch.set_anisotropy("cubic", ax, np.nan, 0.0)
     ch.set_anisotropy("cubic", ax, 1e4, 0.0)
     ch.set_anisotropy("uniaxial", me_scaling=True)
+
+
+def test_uniaxial_temperature_law(O, mmc):
+    """The me^{l(l+1)/2} law on the uniaxial form (K1 order 2: me^3, K2 order
+    4: me^10): decisions and energy terms against the oracle."""
+    grid, cell = (24, 20, 2), (4e-9, 4e-9, 3e-9)
+    N = int(np.prod(grid))
+    kw = dict(Ms0=1e6, A0=2e-12, K1=2e6, K2=8e5, Tc=700.0, T=560.0, B=(0.0, 0.02, 0.05), seed=29,
+              easy_axis=(0.2, -0.3, 0.9))
+    ch = mmc.Chain(grid, cell, **kw)
+    ch.set_anisotropy("uniaxial", me_scaling=True)
+    ref = O.System(grid, cell, kscale=True, **kw)
+    m0 = (workloads.random_state(N, seed=70, lmin=1.0, lmax=1.0) * ref.coeffs()["m0"]).astype(np.float32)
+    for colour in (0, 1):
+        _decision_check(O, ch, ref, m0, sweep=5, colour=colour, cone=60)
+    ch.set_m(m0)
+    terms = ch.energy()[1]
+    Eo = ref.energy(m0.astype(np.float64))
+    assert abs(terms[2] - Eo[2]) < 1e-5 * abs(Eo[2]), (terms[2], Eo[2])
+    unscaled = O.System(grid, cell, **kw).energy(m0.astype(np.float64))[2]
+    assert abs(Eo[2]) < 0.5 * abs(unscaled)         # me < 1: the law lowers the anisotropy
