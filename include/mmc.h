@@ -132,9 +132,17 @@ mmc_status mmc_set_grains(mmc_ctx* ctx, const uint32_t* grain_of_cell, uint32_t 
                           const double* easy_axis3, const double* K1, const double* K2,
                           const double* Tc, double boundary_exchange_scale);
 
+/* Applied field mu0*H (tesla) of the Zeeman term of dF (Sec. II); the state
+ * is kept.  Errors: MMC_ERR_ARG for NULL, MMC_ERR_DOMAIN for non-finite. */
 mmc_status mmc_set_field(mmc_ctx* ctx, const double mu0H_tesla[3]);
-/* Re-solves me(T), chi_par(T), sigma; the state is kept.  Clears per-grain
- * temperatures (every grain at T). */
+/* Chain temperature T > 0 (kelvin).  Re-solves on the host, in FP64, the mean
+ * field at H = 0: me(T) (Eq. 9, or its J = 1/2 Brillouin form) and the
+ * reduced longitudinal susceptibility chi_par(T) (Eq. 8), hence the Eq. 7
+ * coefficients of the longitudinal term and the length-move width sigma
+ * (Eq. 13, capped at 0.03); every kT-scaled constant of dF is rescaled.  The
+ * state is kept; per-grain temperatures are cleared (every grain at T).
+ * Synchronises the context's stream.  Errors: MMC_ERR_DOMAIN for T <= 0 or
+ * non-finite. */
 mmc_status mmc_set_temperature(mmc_ctx* ctx, double T_kelvin);
 
 /* Non-uniform temperature profile (paper Sec. IV, laser-heated films): grain
@@ -181,7 +189,14 @@ mmc_status mmc_set_anisotropy(mmc_ctx* ctx, int32_t kind, const double* axes6, c
 mmc_status mmc_set_m(mmc_ctx* ctx, const float* m, int on_device);
 mmc_status mmc_get_m(mmc_ctx* ctx, float* out, int on_device);
 
-/* Enqueue n full sweeps (n >= 0). */
+/* Enqueue n full sweeps (n >= 0), asynchronously on the context's stream.
+ * One sweep is one MMC iteration (Sec. II, steps 1-4): for colour 0 then 1,
+ * refresh the demag field (Sec. III, Eq. 14) when demag is on, then give every
+ * cell of the colour one trial move (cone rotation, length change) accepted
+ * by Eq. 5; then reduce the sweep's statistics (FP64), adapt the cone every
+ * adapt_every sweeps (Sec. II) and advance the sweep counter, all on the
+ * device.  Errors: MMC_ERR_ARG for n < 0, MMC_ERR_STATE after a device
+ * error, MMC_ERR_DEVICE from a launch. */
 mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n);
 /* As mmc_sweep, and copies per-sweep statistics to host `series` (n*5 doubles:
  * <mx>, <my>, <mz>, <|m|^2> (FP64 reductions) and the accepted-move count). */
@@ -197,8 +212,11 @@ mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series);
  * 2 demag x-inverse FFT, 3 colour pass, 4 end-of-sweep statistics. */
 mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[5], int32_t launches_out[5]);
 
-/* Total free energy (J) and its split {exchange, DMI, anisotropy, Zeeman,
- * longitudinal, demag}, with a freshly computed demag field, FP64 sums. */
+/* Total free energy (J) of the current state and its split {exchange (Eq. 10
+ * as the bond sum), DMI (Eq. 15), anisotropy (Eq. 11 or 12), Zeeman,
+ * longitudinal (kT times the Eq. 7 exponent), demag (-mu0 V Ms0^2 / 2
+ * sum m.h, Eq. 14 with a freshly computed field)}, each summed in FP64.
+ * Synchronises the stream.  Either output may be NULL, not both. */
 mmc_status mmc_energy(mmc_ctx* ctx, double* E_total_J, double E_terms_J[6]);
 
 /* Demag field h = H_d/Ms0 of the current state, natural SoA (3*N floats). */
@@ -221,10 +239,12 @@ typedef struct {
     double m2_mean;           /* <|m|^2> after the last sweep */
     uint64_t accepts_last;    /* accepted moves in the last sweep */
 } mmc_stats;
+/* Run statistics of the chain after the work queued so far (synchronises the
+ * stream): the sweep counter, the accept window and cone angle of the
+ * adaptation rule (Sec. II), sigma (Eq. 13) and me (Eq. 9) of class 0, and
+ * the FP64 means <m>, <|m|^2> and accepted-move count of the last sweep. */
 mmc_status mmc_get_stats(mmc_ctx* ctx, mmc_stats* out);
 
-/* Run state for checkpoint/resume: with the state m this restores a chain
- * bit-exactly (the generator is stateless). */
 /* Running averages for averaging over chunks of sweeps (the hysteresis-loop
  * rule of Sec. III: chunk averages of the magnetization): every sweep adds
  * its <mx>, <my>, <mz>, <|m|^2> (FP64 means of the sweep's end state) to
@@ -233,6 +253,11 @@ mmc_status mmc_get_stats(mmc_ctx* ctx, mmc_stats* out);
  * averages over the sweeps since the previous call (zeros when n_out = 0) and
  * their count, and resets the accumulators. */
 mmc_status mmc_take_averages(mmc_ctx* ctx, double avg_out[4], uint64_t* n_out);
+
+/* Run state for checkpoint/resume: the sweep counter, cone angle and accept
+ * window; with the state m (mmc_get_m / mmc_set_m) this restores a chain
+ * bit-exactly (the generator is stateless).  get synchronises the stream;
+ * set needs cone_deg in [1, 180] (else MMC_ERR_ARG). */
 mmc_status mmc_get_state(mmc_ctx* ctx, uint64_t* sweep, int32_t* cone_deg, uint64_t* accepts_window);
 mmc_status mmc_set_state(mmc_ctx* ctx, uint64_t sweep, int32_t cone_deg, uint64_t accepts_window);
 
@@ -242,9 +267,12 @@ mmc_status mmc_set_state(mmc_ctx* ctx, uint64_t sweep, int32_t cone_deg, uint64_
  * chain per grid row of blocks; the shape groups run on streams of their
  * own.  mmc_batch_sweep enqueues n sweeps of every chain as one HIP graph
  * launch on the first chain's stream (captured on the first call and again
- * whenever n or a chain's temperature, field or grains changed); chains stay
- * caller-owned, must outlive the batch and must not be used directly while a
- * batch sweep runs.  All chains must be on the same device.  Results equal
+ * whenever n or a chain's temperature, field or grains changed).  Work
+ * enqueued on a chain's own stream before the call (mmc_sweep, say) runs
+ * before the batch's sweeps, and work enqueued on it after the call (getters,
+ * sweeps) runs after them; chains stay caller-owned, must outlive the batch
+ * and must not be changed from another thread while a batch call runs.  All
+ * chains must be on the same device.  Results equal
  * running each chain alone, bit for bit.  Errors: MMC_ERR_ARG (NULL, empty,
  * repeated chain, chains on different devices), MMC_ERR_STATE (a chain had a
  * device error), MMC_ERR_DEVICE / MMC_ERR_OOM from HIP. */

@@ -104,7 +104,9 @@ struct mmc_batch {
     std::vector<BatchGroup> groups;
     std::vector<hipStream_t> streams;     // one per group
     std::vector<hipEvent_t> done;
+    std::vector<hipEvent_t> chain_ev;     // per chain: orders its own stream against the batch launch
     hipEvent_t fork = nullptr;
+    hipEvent_t joined = nullptr;          // recorded on the first chain's stream after a launch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_n = -1;
@@ -742,7 +744,11 @@ mmc_status mmc_batch_create(mmc_ctx* const* chains, int32_t n, mmc_batch** out) 
     if (!b) return fail(MMC_ERR_OOM, "host allocation failed");
     b->ch.assign(chains, chains + n);
     HIPCK(hipSetDevice(chains[0]->device));
-    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b->joined, hipEventDisableTiming) == hipSuccess;
+    b->chain_ev.assign(n, nullptr);
+    for (int i = 0; ok && i < n; ++i) ok = hipEventCreateWithFlags(&b->chain_ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
         mmc_batch_destroy(b);
         return fail(MMC_ERR_DEVICE, "event creation failed");
     }
@@ -833,7 +839,17 @@ mmc_status mmc_batch_sweep(mmc_batch* b, int32_t n) {
         b->versions.resize(b->ch.size());
         for (size_t i = 0; i < b->ch.size(); ++i) b->versions[i] = b->ch[i]->version;
     }
+    // work queued earlier on a chain's own stream (mmc_sweep, setters) runs
+    // before the graph, and later work on that stream (getters, sweeps) after it
+    for (size_t i = 0; i < b->ch.size(); ++i) {
+        if (b->ch[i]->stream == s0) continue;
+        HIPCK(hipEventRecord(b->chain_ev[i], b->ch[i]->stream));
+        HIPCK(hipStreamWaitEvent(s0, b->chain_ev[i], 0));
+    }
     HIPCK(hipGraphLaunch(b->exec, s0));
+    HIPCK(hipEventRecord(b->joined, s0));
+    for (auto* c : b->ch)
+        if (c->stream != s0) HIPCK(hipStreamWaitEvent(c->stream, b->joined, 0));
     for (auto* c : b->ch) c->host_sweep += (unsigned long long)n;
     return MMC_OK;
 }
@@ -856,7 +872,9 @@ void mmc_batch_destroy(mmc_batch* b) {
     for (auto& g : b->groups) if (g.d_list) (void)hipFree(g.d_list);
     for (auto s : b->streams) if (s) (void)hipStreamDestroy(s);
     for (auto e : b->done) if (e) (void)hipEventDestroy(e);
+    for (auto e : b->chain_ev) if (e) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->joined) (void)hipEventDestroy(b->joined);
     delete b;
 }
 

@@ -4,8 +4,8 @@ the full size of its granular Fe film leg.
 
 * demag field: sampled cells against the oracle's direct sum over all 4.2 M
   source cells (relative error per sampled vector <= 1e-5 of the field scale);
-* one colour pass, whole grid: identical decisions except where the oracle's
-  log-acceptance margin is within the FP32 tolerance.
+* one colour pass, whole grid: identical decisions except for moves within
+  1e-5 of the acceptance cut-off (the oracle's log-acceptance margin).
 """
 import numpy as np
 import pytest
@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 GRID, CELL = (1024, 1024, 4), (5e-9, 5e-9, 5e-9)
 MAT = dict(Ms0=1e6, A0=1e-11, K1=5e5, Tc=700.0)
+DECISION_TOL = 1e-5     # |k ln f - dF/kT - ln u3| of a move whose decisions may differ
 
 
 @pytest.fixture(scope="module")
@@ -68,7 +69,7 @@ def test_colour_pass_whole_grid(chain):
         worst = np.abs(margin[mism]).max() if mism.any() else 0.0
         print("colour %d: %d cells, %d accepted, %d mismatches, worst |margin| %.2e"
               % (colour, mine.sum(), (acc_o == 1).sum(), mism.sum(), worst))
-        assert worst < 2e-4
+        assert worst < DECISION_TOL
 
 
 def test_fe_film_colour_pass_whole_grid():
@@ -109,5 +110,5 @@ def test_fe_film_colour_pass_whole_grid():
         worst = np.abs(margin[mism]).max() if mism.any() else 0.0
         print("colour %d: %d cells, %d accepted, %d mismatches, worst |margin| %.2e"
               % (colour, mine.sum(), (acc_o == 1).sum(), mism.sum(), worst))
-        assert worst < 2e-4
+        assert worst < DECISION_TOL
     ch.close()

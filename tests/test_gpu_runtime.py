@@ -28,30 +28,125 @@ def _chains(pkg, specs):
 
 
 def test_batch_equals_sequential(pkg):
-    specs = workloads.batch_chain_params(6, seed=0)
-    for s in specs:                      # keep the test small: shrink the large grids
-        s["grid"] = tuple(min(v, 96) for v in s["grid"][:2]) + (s["grid"][2],)
+    """The batched workload's chain shapes at their real sizes (64^2x1,
+    128^2x1, 256^2x2, 512^2x2 cells of 5 nm), uneven T and field, demag on
+    (off for one chain): batched sweeps equal the chains run alone, bit for bit."""
+    specs = workloads.batch_chain_params(8, seed=0)
+    for i, s in enumerate(specs):        # every size twice
+        s["grid"] = workloads.BATCH_SIZES[i % 4]
     specs[0]["demag"] = False
+    print("chains", [(s["grid"], round(s["T"]), s["B"][2]) for s in specs], flush=True)
     a = _chains(pkg, specs)
     b = _chains(pkg, specs)
     batch = pkg.Batch(a)
-    batch.sweep(7)
-    batch.sweep(7)                        # replay of the captured graph
+    batch.sweep(3)
+    batch.sweep(3)                        # replay of the captured graph
     batch.sync()
     for c in b:
-        c.sweep(14)
+        c.sweep(6)
     for ca, cb in zip(a, b):
         assert np.array_equal(ca.get_m(), cb.get_m())
         sa, sb = ca.stats(), cb.stats()
-        assert sa["sweeps"] == sb["sweeps"] == 14
+        assert sa["sweeps"] == sb["sweeps"] == 6
         assert sa["accepts_last"] == sb["accepts_last"] and sa["cone_deg"] == sb["cone_deg"]
+        assert sa["m2_mean"] == sb["m2_mean"]
     # changing a chain's field rebuilds the graph; results still match
     a[1].set_field((0, 0, 0.3))
     b[1].set_field((0, 0, 0.3))
-    batch.sweep(3)
+    batch.sweep(2)
     batch.sync()
-    b[1].sweep(3)
+    b[1].sweep(2)
     assert np.array_equal(a[1].get_m(), b[1].get_m())
+    batch.close()
+
+
+def test_batch_orders_chain_streams(pkg):
+    """Sweeps queued on a chain's own stream before a batch call run before
+    the batch's sweeps, and a getter after it sees them (no explicit sync in
+    between, graph replayed unchanged)."""
+    specs = workloads.batch_chain_params(3, seed=1)
+    for i, s in enumerate(specs):
+        s["grid"] = workloads.BATCH_SIZES[i]
+    a = _chains(pkg, specs)
+    b = _chains(pkg, specs)
+    batch = pkg.Batch(a)
+    batch.sweep(2)                        # captures the graph
+    a[1].sweep(3)                         # on chain 1's own stream, not synchronised
+    a[2].sweep(1)
+    batch.sweep(2)                        # replay: must follow those sweeps
+    a[2].sweep(2)                         # and this must follow the replay
+    got = [c.get_m() for c in a]
+    for c in b:
+        c.sweep(2)
+    b[1].sweep(3)
+    b[2].sweep(1)
+    for c in b:
+        c.sweep(2)
+    b[2].sweep(2)
+    for g, c, n in zip(got, b, (4, 7, 7)):
+        assert c.stats()["sweeps"] == n
+        assert np.array_equal(g, c.get_m())
+    batch.close()
+
+
+def _colour_pass_against_oracle(ref, before, after, colour, sweep, cone, tol=1e-5):
+    """Cells of `colour` in `after` (GPU, float32) against the oracle's colour
+    pass from `before` with a fresh FP64 field: decisions equal outside the
+    1e-5 margin band, accepted values within 2e-6 of |m|."""
+    b64 = before.astype(np.float64)
+    h = ref.demag(b64)
+    _, acc_o, margin, mB, _ = ref.subsweep(b64, sweep, colour, float(cone), h=h)
+    mine = acc_o >= 0
+    acc_g = np.any(after != before, axis=0)
+    assert not acc_g[~mine].any(), "cells of the other colour changed"
+    mism = mine & (acc_g != (acc_o == 1))
+    worst = np.abs(margin[mism]).max() if mism.any() else 0.0
+    both = mine & acc_g & (acc_o == 1)
+    err = (np.abs(after.astype(np.float64) - mB)[:, both].max(axis=0) / np.linalg.norm(b64, axis=0)[both]).max() \
+        if both.any() else 0.0
+    print("  colour %d: %d cells, %d accepted, %d mismatches (worst |margin| %.2e), accepted values %.1e"
+          % (colour, mine.sum(), (acc_o == 1).sum(), mism.sum(), worst, err), flush=True)
+    assert worst < tol
+    assert err < 2e-6
+
+
+def test_batched_sweep_matches_oracle(pkg):
+    """One batched sweep of four chains of the batched workload's shapes
+    (uneven size, T and field; demag refreshed before each colour pass),
+    each from a set state, against the oracle colour pass by colour pass:
+    colour 0 from the set state, colour 1 from the GPU's state after colour 0
+    (its colour-0 cells are final), each with a fresh FP64 demag field."""
+    from oracle import oracle as O
+    specs = workloads.batch_chain_params(4, seed=3)
+    chains, refs, m0s = [], [], []
+    for i, s in enumerate(specs):
+        s["grid"] = workloads.BATCH_SIZES[i]
+        ch = pkg.Chain(s["grid"], (5e-9,) * 3, T=s["T"], B=s["B"], demag=True, seed=7, chain_id=s["chain_id"],
+                       **MAT)
+        ref = O.System(s["grid"], (5e-9,) * 3, T=s["T"], B=s["B"], demag=True, seed=7, chain_id=s["chain_id"], **MAT)
+        N = int(np.prod(s["grid"]))
+        m0 = workloads.perturbed_uniform_state(N, seed=20 + i, L=ref.coeffs()["m0"], spread=0.4)
+        ch.set_m(m0)
+        ch.set_state(1000 + 17 * i, 25 + 10 * i, 0)
+        chains.append(ch)
+        refs.append(ref)
+        m0s.append(m0)
+    batch = pkg.Batch(chains)
+    batch.sweep(1)
+    batch.sync()
+    for i, (ch, ref, m0, s) in enumerate(zip(chains, refs, m0s, specs)):
+        print("chain %d: %s T=%.0f K Bz=%.3f T" % (i, s["grid"], s["T"], s["B"][2]), flush=True)
+        g = ch.get_m()
+        sweep, cone = 1000 + 17 * i, 25 + 10 * i
+        nx, ny, nz = s["grid"]
+        x = np.arange(nx)[None, None, :]
+        y = np.arange(ny)[None, :, None]
+        z = np.arange(nz)[:, None, None]
+        col0 = (((x + y + z) & 1) == 0).reshape(-1)
+        mid = np.where(col0[None, :], g, m0)        # the GPU's state after colour 0
+        _colour_pass_against_oracle(ref, m0, mid, 0, sweep, cone)
+        _colour_pass_against_oracle(ref, mid, g, 1, sweep, cone)
+        assert ch.stats()["sweeps"] == sweep + 1
     batch.close()
 
 
