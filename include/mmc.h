@@ -219,6 +219,23 @@ mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out
  * Synchronises the stream.  Either output may be NULL, not both. */
 mmc_status mmc_energy(mmc_ctx* ctx, double* E_total_J, double E_terms_J[6]);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, hosts that forbid hipMalloc): mmc_energy without any
+ * allocation, host copy or synchronisation.  Enqueues on the context's stream
+ * the demag refresh (when demag is on), the energy kernel and a final FP64
+ * sum, and writes 7 doubles to out_device (device memory on the context's GPU,
+ * owned by the caller): the six terms of mmc_energy in its order, then the
+ * total, in joules, equal to what mmc_energy returns for the same state.
+ * The per-block partial sums go to a static device array of 2048 x 6 doubles
+ * (96 KiB, one copy per GPU, held until the process ends; its address is
+ * looked up once per GPU by mmc_create).  Every call on a GPU shares that
+ * array: calls that overlap on one GPU (contexts on unordered streams) race,
+ * so order them.  The energy kernel strides over the grid with at most 2048
+ * blocks, so every grid size fits; a launch that needed more would be
+ * rejected with MMC_ERR_UNSUPPORTED.  Errors: MMC_ERR_ARG for NULL,
+ * MMC_ERR_STATE after a device error, MMC_ERR_DEVICE from a launch. */
+mmc_status mmc_energy_noalloc(mmc_ctx* ctx, double* out_device);
+
 /* Demag field h = H_d/Ms0 of the current state, natural SoA (3*N floats). */
 mmc_status mmc_demag_field(mmc_ctx* ctx, float* h_out, int on_device);
 

@@ -307,6 +307,14 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
     do {
         ctx->g = *grid; ctx->cs = *cell; ctx->mat = *mat; ctx->run = *run;
         if (hipGetDevice(&ctx->device) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "no HIP device"); break; }
+        // set-up of mmc_energy_noalloc's scratch on this device (once per device)
+        {
+            const hipError_t e = energy_scratch_init(ctx->device);
+            if (e != hipSuccess) {
+                st = fail(MMC_ERR_DEVICE, "energy scratch set-up on device %d: %s", ctx->device, hipGetErrorString(e));
+                break;
+            }
+        }
         if (hip_stream) ctx->stream = (hipStream_t)hip_stream;
         else {
             if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -638,6 +646,23 @@ mmc_status mmc_energy(mmc_ctx* ctx, double* E_total, double E_terms[6]) {
     for (int k = 0; k < 6; ++k) { t[k] *= kT; tot += t[k]; }
     if (E_terms) for (int k = 0; k < 6; ++k) E_terms[k] = t[k];
     if (E_total) *E_total = tot;
+    return MMC_OK;
+}
+
+mmc_status mmc_energy_noalloc(mmc_ctx* ctx, double* out_device) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!out_device) return fail(MMC_ERR_ARG, "NULL output");
+    double* part = energy_scratch(ctx->device);
+    if (!part) return fail(MMC_ERR_STATE, "energy scratch of device %d is not set up", ctx->device);
+    const long long blocks = std::min<long long>((ctx->N + 255) / 256, kEnergyMaxBlocks);
+    if (blocks > kEnergyMaxBlocks)
+        return fail(MMC_ERR_UNSUPPORTED, "energy needs %lld partial sums, the scratch holds %d", blocks, kEnergyMaxBlocks);
+    if (ctx->demag) HIPCK(launch_demag(ctx->args, ctx->plan, single(ctx), 3, ctx->d_tw, ctx->stream));
+    int nb = 0;
+    HIPCK(launch_energy(ctx->args, ctx->has_classes, ctx->cubic, ctx->d_ctab, ctx->d_cid, ctx->d_m,
+                        ctx->demag ? ctx->d_h : nullptr, part, ctx->stream, &nb));
+    HIPCK(launch_energy_sum(part, nb, kB * ctx->run.T, out_device, ctx->stream));
     return MMC_OK;
 }
 

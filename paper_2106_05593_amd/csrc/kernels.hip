@@ -7,6 +7,8 @@
 // ceil(nx/2) slots; cell (x,y,z) has colour (x+y+z)&1 and slot x>>1.
 #include "rng.h"
 
+#include <mutex>
+
 namespace mmc {
 
 // ---------------------------------------------------------------------
@@ -171,11 +173,69 @@ hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s) {
 hipError_t launch_energy(const SweepArgs& a, bool classes, bool cubic, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out) {
     const long long N = (long long)a.nx * a.ny * a.nz;
-    const int blocks = (int)std::min<long long>((N + 255) / 256, 2048);
+    const int blocks = (int)std::min<long long>((N + 255) / 256, kEnergyMaxBlocks);
     *nblk_out = blocks;
     const int cb = cubic ? 1 : 0;
     if (classes) hipLaunchKernelGGL(k_energy<true>, dim3(blocks), dim3(256), 0, s, a, ctab, cid, m, h, part, cb);
     else hipLaunchKernelGGL(k_energy<false>, dim3(blocks), dim3(256), 0, s, a, ctab, cid, m, h, part, cb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Allocation-free energy: the per-block partial sums of k_energy live in a
+// static device array instead of a buffer of the context.  Each GPU holds its
+// own copy until the process ends, and every call on a GPU shares it, so
+// calls that overlap on one GPU race.  Host code takes the array's device
+// address from energy_scratch(), never from its name.
+// ---------------------------------------------------------------------
+static __device__ __align__(256) double scratch[6 * kEnergyMaxBlocks];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t energy_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the device must be current
+    double* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+double* energy_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+// Sum of the nb block partials per term in block order, times kT, and their
+// total in term order: the same operations, in the same order, as the host
+// sum of mmc_energy, so both give the same doubles.
+__global__ void k_energy_sum(const double* __restrict__ part, int nb, double kT, double* __restrict__ out) {
+#pragma clang fp contract(off)
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double t[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < 6; ++k) t[k] += part[6 * b + k];
+    double tot = 0;
+    for (int k = 0; k < 6; ++k) {
+        t[k] *= kT;
+        tot += t[k];
+        out[k] = t[k];
+    }
+    out[6] = tot;
+}
+
+hipError_t launch_energy_sum(const double* part, int nb, double kT, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(64), 0, s, part, nb, kT, out);
     return hipGetLastError();
 }
 

@@ -140,5 +140,16 @@ hipError_t launch_end_sweep(const Chains& c, int shift, long long N, double* ser
 hipError_t launch_energy(const SweepArgs& a, bool classes, bool cubic, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out);
 hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s);
+// Energy partials: k_energy never runs more than kEnergyMaxBlocks blocks
+// (it strides over the grid).
+constexpr int kEnergyMaxBlocks = 2048;
+// Allocation-free energy (kernels.hip): energy_scratch_init(device), called
+// with that device current, looks up the device address of the static
+// partial-sum array once per device; energy_scratch(device) returns it (NULL
+// before the set-up).  launch_energy_sum writes the six terms times kT and
+// their total (7 doubles) to out.
+hipError_t energy_scratch_init(int device);
+double* energy_scratch(int device);
+hipError_t launch_energy_sum(const double* part, int nb, double kT, double* out, hipStream_t s);
 
 }  // namespace mmc

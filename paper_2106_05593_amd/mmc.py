@@ -74,6 +74,7 @@ _SIGS = {
     "mmc_sweep_record": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "mmc_sweep_timed": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "mmc_energy": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "mmc_energy_noalloc": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mmc_demag_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_subsweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mmc_get_stats": (C.c_int, [C.c_void_p, C.POINTER(mmc_stats)]),
@@ -265,6 +266,15 @@ class Chain:
         terms = (C.c_double * 6)()
         _check(lib().mmc_energy(self._h, C.byref(tot), terms))
         return tot.value, np.array(terms[:])
+
+    def energy_noalloc(self, out):
+        """mmc_energy_noalloc: enqueue the energy into out (torch CUDA float64
+        tensor of 7 elements: six terms, then the total); no allocation, no sync."""
+        if out.dtype != np.float64 and str(out.dtype) != "torch.float64":
+            raise TypeError("out must be float64")
+        if not out.is_cuda or out.numel() < 7 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous CUDA tensor of at least 7 elements")
+        _check(lib().mmc_energy_noalloc(self._h, _dptr(out)))
 
     def demag_field(self):
         a = np.empty((3, self.N), dtype=np.float32)
