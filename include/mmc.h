@@ -81,9 +81,22 @@ typedef enum {
                             the exact Metropolis-Hastings ratio for the Eq. 1 target */
 } mmc_lenmove;
 
+/* Demag term (Sec. III, Eq. 14) and the precision of its FFT convolution.
+ * The tensor spectrum is computed in FP64 and stored in FP32; the x-direction
+ * transforms and the layer mixing run in FP32 in every mode.  The split modes
+ * run the radix-16 DFT stages of the y-direction transforms on the matrix
+ * cores with each operand split into a high and a low 16-bit part and the
+ * products hi*hi + hi*lo + lo*hi accumulated in FP32: BF16 parts keep 16
+ * significant bits per operand, FP16 parts 22 (each stage's inputs scaled by a
+ * power of two that keeps them in FP16 range).  The split modes need an even
+ * nz and a padded y length (the power of two >= 2 ny - 1) of 512, 1024 or
+ * 2048 (nz = 2, 4) or 256 or 1024 (nz = 6, 8); other shapes give
+ * MMC_ERR_UNSUPPORTED. */
 typedef enum {
     MMC_DEMAG_OFF = 0,
-    MMC_DEMAG_FP32 = 1          /* FFT convolution in FP32, tensor spectrum from FP64 */
+    MMC_DEMAG_FP32 = 1,         /* FFT convolution in FP32 */
+    MMC_DEMAG_SPLIT_BF16 = 2,   /* y-direction DFT stages as split BF16 matrix products */
+    MMC_DEMAG_SPLIT_FP16 = 3    /* y-direction DFT stages as split FP16 matrix products, scaled per stage */
 } mmc_demag;
 
 typedef struct {

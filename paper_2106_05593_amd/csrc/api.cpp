@@ -288,7 +288,7 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
     if (run->cone_deg < 1 || run->cone_deg > 180) return fail(MMC_ERR_ARG, "cone_deg must be in [1, 180]");
     if (run->adapt_every < 0) return fail(MMC_ERR_ARG, "adapt_every must be >= 0");
     if (run->lenmove != MMC_LEN_PAPER && run->lenmove != MMC_LEN_EXACT) return fail(MMC_ERR_ARG, "unknown lenmove");
-    if (run->demag != MMC_DEMAG_OFF && run->demag != MMC_DEMAG_FP32) return fail(MMC_ERR_ARG, "unknown demag mode");
+    if (run->demag < MMC_DEMAG_OFF || run->demag > MMC_DEMAG_SPLIT_FP16) return fail(MMC_ERR_ARG, "unknown demag mode");
     if (run->refresh_per_sweep != 1 && run->refresh_per_sweep != 2) return fail(MMC_ERR_ARG, "refresh_per_sweep must be 1 or 2");
     if (run->init != 0 && run->init != 1) return fail(MMC_ERR_ARG, "init must be 0 or 1");
     if (!(run->sigma_fixed < 1.0)) return fail(MMC_ERR_DOMAIN, "sigma_fixed must be < 1");
@@ -299,6 +299,10 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
         const int Py = pad_pow2(grid->ny, 1);
         if (3 * grid->nz * ypass_E(grid->nz, Py) > 96)
             return fail(MMC_ERR_UNSUPPORTED, "demag: padded ny %d with nz %d exceeds the y-pass register budget", Py, grid->nz);
+        if (run->demag >= MMC_DEMAG_SPLIT_BF16 && !ypass_split_ok(grid->nz, Py))
+            return fail(MMC_ERR_UNSUPPORTED,
+                        "split-precision demag needs an even nz and a padded y length of 512, 1024 or 2048 "
+                        "(nz = 2, 4) or 256 or 1024 (nz = 6, 8); got nz %d, padded y %d", grid->nz, Py);
     }
 
     ctx = new (std::nothrow) mmc_ctx();
@@ -371,6 +375,9 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
             p.S = 3 * grid->nz;
             std::vector<float> K;
             tensor_spectrum(grid->nx, grid->ny, grid->nz, cell->hx, cell->hy, cell->hz, p.Px, p.Py, K);
+            p.prec = run->demag == MMC_DEMAG_SPLIT_BF16 ? 1 : (run->demag == MMC_DEMAG_SPLIT_FP16 ? 2 : 0);
+            p.kmax = 0.f;
+            for (float kv : K) p.kmax = std::max(p.kmax, std::fabs(kv));
             if (!alloc((void**)&p.K, sizeof(float) * K.size())) break;
             if (hipMemcpy(p.K, K.data(), sizeof(float) * K.size(), hipMemcpyHostToDevice) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "copy"); break; }
             if (!alloc((void**)&p.X, sizeof(float2) * (size_t)(p.L + 1) * p.S * grid->ny)) break;
@@ -793,6 +800,7 @@ static bool same_shape(const mmc_ctx* a, const mmc_ctx* c) {
     return a->g.nx == c->g.nx && a->g.ny == c->g.ny && a->g.nz == c->g.nz && a->cs.hx == c->cs.hx &&
            a->cs.hy == c->cs.hy && a->cs.hz == c->cs.hz && a->has_classes == c->has_classes &&
            a->demag == c->demag && (!a->demag || a->run.refresh_per_sweep == c->run.refresh_per_sweep) &&
+           a->run.demag == c->run.demag &&
            a->run.lenmove == c->run.lenmove && (a->mat.D0 != 0.0) == (c->mat.D0 != 0.0) && a->cubic == c->cubic;
 }
 

@@ -16,6 +16,7 @@ extern template hipError_t launch_ypass_nz<7>(const Chains&, const DemagPlan&, c
 extern template hipError_t launch_ypass_nz<8>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
 
 int ypass_E(int nz, int Py) { return y_E(nz, Py); }
+bool ypass_split_ok(int nz, int Py) { return ysplit_ok(nz, Py); }
 
 template <int L>
 static hipError_t launch_x_L(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int mask,

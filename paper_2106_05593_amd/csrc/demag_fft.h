@@ -154,9 +154,10 @@ __device__ __forceinline__ void build_twiddles(float2* tab, const float2* __rest
 // v[S0..S0+NS).  Non-final passes write to LDS (signal s at lds + s*ls); the
 // final pass leaves its outputs in registers.  With the skew-16 layout the
 // RHO outputs of a butterfly land at lpad(base) + r*NSUB + (r*NSUB >> 4) for
-// every power-of-two NSUB, so one address per butterfly suffices.
+// every power-of-two NSUB, so one address per butterfly suffices.  ptab: this
+// pass's twiddle table, entry (r-1)*NSUB + k (unused when NSUB = 1).
 template <int N, int E, int RHO, int NSUB, bool INV, bool LAST, int NS, int S0, int S>
-__device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* tab, float2* lds, int ls) {
+__device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* ptab, float2* lds, int ls) {
     constexpr int T = N / E;
     constexpr int Q = E / RHO;
 #pragma unroll
@@ -165,7 +166,7 @@ __device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* 
         const int k = b & (NSUB - 1);
         float2 w[RHO];
         if constexpr (NSUB > 1) {
-            const float2* twk = tab + tw_off(N, E, NSUB) + k;
+            const float2* twk = ptab + k;
 #pragma unroll
             for (int r = 1; r < RHO; ++r) w[r] = twk[(r - 1) * NSUB];
         }
@@ -197,7 +198,7 @@ __device__ __forceinline__ void st_passes(float2 (&v)[S][E], int j, const float2
         constexpr int RHO = (N / NSUB) < E ? (N / NSUB) : E;
         constexpr bool LAST = NSUB * RHO >= N;
         if constexpr (!LAST) __syncthreads();   // earlier readers of lds are done
-        st_pass<N, E, RHO, NSUB, INV, LAST, NS, S0, S>(v, j, tab, lds, ls);
+        st_pass<N, E, RHO, NSUB, INV, LAST, NS, S0, S>(v, j, tab + tw_off(N, E, NSUB), lds, ls);
         if constexpr (!LAST) {
             __syncthreads();
             const int rb = lpad(j);
@@ -626,6 +627,336 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const 
 }
 
 // ---------------------------------------------------------------------
+// Split-precision DFT stages on the matrix cores (y pass, MMC_DEMAG_SPLIT_*).
+//
+// A radix-16 Stockham pass is a product of the 16-point DFT matrix with a
+// 16 x 16 block of butterflies: as real arithmetic, C[q][b] = sum_kk A[q][kk]
+// B[kk][b] with kk = 2r + (0: real part, 1: imaginary part) of the r-th
+// (twiddled) input of butterfly b, one product for the real outputs (A_re)
+// and one for the imaginary outputs (A_im), v_mfma_f32_16x16x32 each.  Both
+// operands are split into a high and a low 16-bit part (x = hi + lo), and
+// each product sums hi*hi + hi*lo + lo*hi in FP32 (the lo*lo term is below
+// the rounding of hi + lo).  BF16 parts keep 16 significant bits of each
+// operand; FP16 parts keep 22 but have the range of FP16, so the FP16 form
+// scales each pass's inputs by a power of two chosen from a bound on their
+// magnitude (exact, undone on the outputs).
+//
+// Operand layouts of v_mfma_f32_16x16x32_{bf16,f16} (wave64): lane l holds
+// A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e < 8, and
+// C[4 (l / 16) + e][l % 16], e < 4.  So lane (c = l % 16, g = l / 16) loads
+// inputs r = 4g .. 4g+3 of butterfly c of the block and writes outputs q =
+// 4g .. 4g+3 of the same butterfly.
+// ---------------------------------------------------------------------
+typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 mf_f16x8 __attribute__((ext_vector_type(8)));
+typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
+
+// PREC: 0 FP32 transforms on the vector units, 1 split BF16, 2 split FP16.
+template <int PREC> struct MfOps;
+template <> struct MfOps<1> {
+    typedef __bf16 S;
+    typedef mf_bf16x8 V;
+    static __device__ __forceinline__ mf_f32x4 mma(V a, V b, mf_f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MfOps<2> {
+    typedef _Float16 S;
+    typedef mf_f16x8 V;
+    static __device__ __forceinline__ mf_f32x4 mma(V a, V b, mf_f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// x*sc = hi + lo (sc: a power of two; 1 in the BF16 form).  BF16: hi is x
+// truncated to its top 16 bits (exact as FP32, packed two per register by a
+// byte permute), lo the exact remainder rounded to BF16.  FP16: hi = f16(x sc),
+// lo = f16(x sc - hi), each one mixed-precision FMA.
+template <int PREC>
+__device__ __forceinline__ void mf_split8(const float (&x)[8], float sc, typename MfOps<PREC>::V& hi,
+                                          typename MfOps<PREC>::V& lo) {
+    if constexpr (PREC == 1) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint32_t u0 = __float_as_uint(x[2 * p]), u1 = __float_as_uint(x[2 * p + 1]);
+            hw[p] = __builtin_amdgcn_perm(u1, u0, 0x07060302u);   // top halves of u0 (low), u1 (high)
+            f2v r;
+            r.x = x[2 * p] - __uint_as_float(u0 & 0xffff0000u);
+            r.y = x[2 * p + 1] - __uint_as_float(u1 & 0xffff0000u);
+            const b2v lb = __builtin_convertvector(r, b2v);
+            lw[p] = __builtin_bit_cast(uint32_t, lb);
+        }
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        const u4v H = {hw[0], hw[1], hw[2], hw[3]}, Lo = {lw[0], lw[1], lw[2], lw[3]};
+        hi = __builtin_bit_cast(typename MfOps<PREC>::V, H);
+        lo = __builtin_bit_cast(typename MfOps<PREC>::V, Lo);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const _Float16 h = (_Float16)(x[e] * sc);
+            hi[e] = h;
+            lo[e] = (_Float16)fmaf(x[e], sc, -(float)h);
+        }
+    }
+}
+
+// The 16-point DFT matrix of one direction in the A layout, split, as two
+// 16 x 32 halves: half h has rows i = 2 (q - 8h) + part for the outputs q of
+// 8h .. 8h+7 (part 0 real, 1 imaginary), so the accumulator of lane (c, g)
+// holds (re, im) of outputs 8h + 2g and 8h + 2g + 1 of butterfly c.
+template <int PREC> struct MfDft {
+    typename MfOps<PREC>::V h0, l0, h1, l1;
+};
+// tw: base table exp(-2 pi i t / TW_N); lane = thread index mod 64.
+template <int PREC, bool INV>
+__device__ __forceinline__ MfDft<PREC> mf_dft16(int lane, const float2* __restrict__ tw) {
+    const int i = lane & 15, po = i & 1;
+    float a0[8], a1[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = 8 * h + (i >> 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int kk = 8 * (lane >> 4) + e, r = kk >> 1, pi = kk & 1;
+            const float2 w = tw[((r * q) & 15) * (TW_N / 16)];   // (cos t, -sin t), t = 2 pi r q / 16
+            const float c = w.x, sn = -w.y;
+            // forward, y = sum x e^{-it}: re = xr c + xi sn, im = xi c - xr sn;
+            // inverse, y = sum x e^{+it}: re = xr c - xi sn, im = xi c + xr sn
+            const float sg = INV ? -1.0f : 1.0f;
+            const float val = po == 0 ? (pi == 0 ? c : sg * sn) : (pi == 0 ? -sg * sn : c);
+            (h == 0 ? a0 : a1)[e] = val;
+        }
+    }
+    MfDft<PREC> A;
+    mf_split8<PREC>(a0, 1.0f, A.h0, A.l0);
+    mf_split8<PREC>(a1, 1.0f, A.h1, A.l1);
+    return A;
+}
+
+// Pass structure of a length-N transform with E elements per thread:
+// forward: radix-E pass (vector units; its inputs past N/2 are the zero
+// padding), mf_kf radix-16 passes on the matrix cores, then a radix-mf_rf pass
+// on the vector units if mf_rf > 1; inverse: mf_ki radix-16 passes, then a
+// radix-mf_ri pass (vector units, only the cropped outputs kept).
+constexpr int mf_pow16(int k) { return k == 0 ? 1 : 16 * mf_pow16(k - 1); }
+constexpr int mf_kf(int N, int E) { return (N / E) >= 256 ? 2 : ((N / E) >= 16 ? 1 : 0); }
+constexpr int mf_rf(int N, int E) { return N / (E * mf_pow16(mf_kf(N, E))); }
+constexpr int mf_ki(int N, int E) { return (N / E) > 16 ? 2 : 1; }
+constexpr int mf_ri(int N, int E) { return N / mf_pow16(mf_ki(N, E)); }
+// Twiddle tables of the split transforms (in LDS): radix-16 pass with
+// sub-size NSUB: 16*NSUB entries, entry r*NSUB + k = exp(-2 pi i r k / (16 NSUB));
+// vector pass of radix R and sub-size N/R: (R-1)*(N/R) entries, (r-1)*NSUB + k.
+// Order: forward passes 1, 2, forward vector pass, inverse pass 2, inverse vector pass.
+constexpr int mf_len_f1(int N, int E) { return mf_kf(N, E) >= 1 ? 16 * E : 0; }
+constexpr int mf_len_f2(int N, int E) { return mf_kf(N, E) >= 2 ? 16 * 16 * E : 0; }
+constexpr int mf_len_fl(int N, int E) { return mf_rf(N, E) > 1 ? (mf_rf(N, E) - 1) * (N / mf_rf(N, E)) : 0; }
+constexpr int mf_len_i2(int N, int E) { return mf_ki(N, E) >= 2 ? 16 * 16 : 0; }
+constexpr int mf_len_il(int N, int E) { return mf_ri(N, E) > 1 ? (mf_ri(N, E) - 1) * (N / mf_ri(N, E)) : 0; }
+constexpr int mf_off_f2(int N, int E) { return mf_len_f1(N, E); }
+constexpr int mf_off_fl(int N, int E) { return mf_off_f2(N, E) + mf_len_f2(N, E); }
+constexpr int mf_off_i2(int N, int E) { return mf_off_fl(N, E) + mf_len_fl(N, E); }
+constexpr int mf_off_il(int N, int E) { return mf_off_i2(N, E) + mf_len_i2(N, E); }
+constexpr int mf_tw_len(int N, int E) { return mf_off_il(N, E) + mf_len_il(N, E); }
+
+template <int NSUB, int RHO, bool ZERO_ROW>
+__device__ __forceinline__ float2 mf_tw_entry(int i, const float2* __restrict__ tw) {
+    // ZERO_ROW: entry r*NSUB + k (r from 0); else (r-1)*NSUB + k
+    const int r = i / NSUB + (ZERO_ROW ? 0 : 1), k = i % NSUB;
+    return tw[(r * k) * (TW_N / (NSUB * RHO))];
+}
+// (FP16 form: the tables of the second radix-16 pass of each direction are
+// scaled by 1/16, which keeps that pass's inputs within the bound of the first)
+template <int N, int E, int NT, int PREC>
+__device__ __forceinline__ void mf_build_twiddles(float2* tab, const float2* __restrict__ tw) {
+    constexpr int LEN = mf_tw_len(N, E);
+    constexpr float S2 = PREC == 2 ? 0.0625f : 1.0f;
+    for (int i = threadIdx.x; i < LEN; i += NT) {
+        float2 v;
+        if (i < mf_off_f2(N, E)) v = mf_tw_entry<E, 16, true>(i, tw);
+        else if (i < mf_off_fl(N, E)) {
+            v = mf_tw_entry<16 * E, 16, true>(i - mf_off_f2(N, E), tw);
+            v.x *= S2;
+            v.y *= S2;
+        }
+        else if (i < mf_off_i2(N, E))
+            v = mf_tw_entry<N / (mf_rf(N, E) > 1 ? mf_rf(N, E) : 1), (mf_rf(N, E) > 1 ? mf_rf(N, E) : 1), false>(
+                i - mf_off_fl(N, E), tw);
+        else if (i < mf_off_il(N, E)) {
+            v = mf_tw_entry<16, 16, true>(i - mf_off_i2(N, E), tw);
+            v.x *= S2;
+            v.y *= S2;
+        }
+        else
+            v = mf_tw_entry<N / (mf_ri(N, E) > 1 ? mf_ri(N, E) : 1), (mf_ri(N, E) > 1 ? mf_ri(N, E) : 1), false>(
+                i - mf_off_il(N, E), tw);
+        tab[i] = v;
+    }
+}
+
+// One radix-16 Stockham pass on the matrix cores over the NSG signals of one
+// thread set (T threads, signal s at lds + s*ls, slots lpad(i)), in place:
+// every wave reads the inputs of its blocks of 16 butterflies, the block
+// synchronises, then each block is twiddled, scaled by sc, split and
+// multiplied, and its outputs (times isc) are written.  ptab: 16*NSUB
+// twiddles, entry r*NSUB + k.
+template <int N, int NSUB, bool INV, int PREC, int NSG, int T>
+__device__ __forceinline__ void mf_pass(float2* lds, int ls, const float2* ptab, int jt, const MfDft<PREC>& A,
+                                        float sc) {
+    constexpr int NB = N / 16;           // butterflies per signal
+    constexpr int GPS = NB / 16;         // blocks of 16 butterflies per signal
+    constexpr int WV = T / 64;           // waves per set
+    static_assert(GPS >= 1 && (NSG * GPS) % WV == 0, "whole blocks per wave");
+    constexpr int NGW = NSG * GPS / WV;  // blocks per wave
+    const int w = jt >> 6, l = jt & 63, c = l & 15, g = l >> 4;
+    float2 in[NGW][4];
+#pragma unroll
+    for (int i = 0; i < NGW; ++i) {
+        const int gi = w + WV * i, s = gi / GPS, b = 16 * (gi % GPS) + c;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) in[i][t] = lds[s * ls + lpad(b + (4 * g + t) * NB)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NGW; ++i) {
+        const int gi = w + WV * i, s = gi / GPS, b = 16 * (gi % GPS) + c;
+        const int k = b & (NSUB - 1);
+        float x[8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float2 a = in[i][t];
+            if constexpr (NSUB > 1) {
+                const float2 wv = ptab[(4 * g + t) * NSUB + k];
+                a = INV ? cmulc(a, wv) : cmul(a, wv);
+            }
+            x[2 * t] = a.x;
+            x[2 * t + 1] = a.y;
+        }
+        typename MfOps<PREC>::V bh, bl;
+        mf_split8<PREC>(x, sc, bh, bl);
+        mf_f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+        c0 = MfOps<PREC>::mma(A.l0, bh, c0);
+        c0 = MfOps<PREC>::mma(A.h0, bl, c0);
+        c0 = MfOps<PREC>::mma(A.h0, bh, c0);
+        c1 = MfOps<PREC>::mma(A.l1, bh, c1);
+        c1 = MfOps<PREC>::mma(A.h1, bl, c1);
+        c1 = MfOps<PREC>::mma(A.h1, bh, c1);
+        const int ob = (b - k) * 16 + k;
+        float2* o = lds + s * ls;
+        // outputs q = 2g, 2g+1 (c0) and 8+2g, 9+2g (c1)
+        o[lpad(ob + (2 * g) * NSUB)] = make_float2(c0[0], c0[1]);
+        o[lpad(ob + (2 * g + 1) * NSUB)] = make_float2(c0[2], c0[3]);
+        o[lpad(ob + (2 * g + 8) * NSUB)] = make_float2(c1[0], c1[1]);
+        o[lpad(ob + (2 * g + 9) * NSUB)] = make_float2(c1[2], c1[3]);
+    }
+}
+
+// Scales of the FP16 form (powers of two): the bound b on the first
+// radix-16 pass's inputs of a direction is mapped to at most 2^14; the second
+// pass's inputs stay within it through its 1/16 twiddles.  The data keep the
+// scale through the layer mixing (linear) and lose it at the store.
+__device__ __forceinline__ float mf_scale(float b) {
+    int ex;
+    (void)frexpf(b, &ex);                 // b <= 2^ex
+    return ldexpf(1.0f, 14 - ex);
+}
+struct MfScales {
+    float f1;                             // forward pass 1 (the data are unscaled before it)
+    float i1;                             // inverse pass 1, relative to the forward result's scale
+    float out;                            // factor that unscales the inverse result
+};
+
+// Forward split transform of signals [G, G+NSG) of one set (registers in the
+// strided layout, thread j holds points j + T*m), result in the same layout.
+template <int N, int E, int PREC, int NSG, int G, int SH>
+__device__ __forceinline__ void y_fwd_mf(float2 (&v)[SH][E], int j, const float2* tabs, float2* lds, int ls,
+                                         const MfDft<PREC>& A, const MfScales& sc) {
+    constexpr int T = N / E;
+    constexpr int KF = mf_kf(N, E), RF = mf_rf(N, E);
+    __syncthreads();                      // earlier readers of lds are done
+    st_pass<N, E, E, 1, false, false, NSG, G, SH>(v, j, tabs, lds, ls);
+    __syncthreads();
+    if constexpr (KF >= 1) {
+        mf_pass<N, E, false, PREC, NSG, T>(lds, ls, tabs, j, A, sc.f1);
+        __syncthreads();
+    }
+    if constexpr (KF >= 2) {
+        mf_pass<N, 16 * E, false, PREC, NSG, T>(lds, ls, tabs + mf_off_f2(N, E), j, A, 1.0f);
+        __syncthreads();
+    }
+    const int rb = lpad(j);
+#pragma unroll
+    for (int s = 0; s < NSG; ++s)
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            if constexpr (T % 16 == 0) v[G + s][m] = lds[s * ls + rb + m * (T + T / 16)];
+            else v[G + s][m] = lds[s * ls + lpad(j + T * m)];
+        }
+    if constexpr (RF > 1)
+        st_pass<N, E, RF, N / RF, false, true, NSG, G, SH>(v, j, tabs + mf_off_fl(N, E), lds, ls);
+}
+
+// Inverse split transform of signals [G, G+NSG) of one set, then the cropped
+// outputs (points y = j + T*q < ny, q < E/2) times osc go to dst0 + s*ny.
+template <int N, int E, int PREC, int NSG, int G, int SH>
+__device__ __forceinline__ void y_inv_mf_store(float2 (&v)[SH][E], int j, const float2* tabs, float2* lds, int ls,
+                                               const MfDft<PREC>& A, const MfScales& sc, float2* __restrict__ dst0,
+                                               int ny, float osc) {
+    constexpr int T = N / E, QH = E / 2;
+    constexpr int KI = mf_ki(N, E), RI = mf_ri(N, E);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NSG; ++s)
+#pragma unroll
+        for (int m = 0; m < E; ++m) lds[s * ls + lpad(j + T * m)] = v[G + s][m];
+    __syncthreads();
+    mf_pass<N, 1, true, PREC, NSG, T>(lds, ls, tabs, j, A, sc.i1);
+    __syncthreads();
+    if constexpr (KI >= 2) {
+        mf_pass<N, 16, true, PREC, NSG, T>(lds, ls, tabs + mf_off_i2(N, E), j, A, 1.0f);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < NSG; ++s)
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[G + s][m] = lds[s * ls + lpad(j + T * m)];
+    if constexpr (RI > 1)
+        st_pass<N, E, RI, N / RI, true, true, NSG, G, SH>(v, j, tabs + mf_off_il(N, E), lds, ls);
+#pragma unroll
+    for (int s = G; s < G + NSG; ++s) {
+        float2* dst = dst0 + (long long)s * ny;
+#pragma unroll
+        for (int q = 0; q < QH; ++q) {
+            const int y = j + T * q;
+            if (y < ny) {
+                if constexpr (PREC == 2) dst[y] = make_float2(v[s][q].x * osc, v[s][q].y * osc);
+                else dst[y] = v[s][q];
+            }
+        }
+    }
+}
+
+template <int N, int E, int PREC, int NSG, int G, int SH>
+__device__ __forceinline__ void y_fwd_mf_groups(float2 (&v)[SH][E], int j, const float2* tabs, float2* lds, int ls,
+                                                const MfDft<PREC>& A, const MfScales& sc) {
+    if constexpr (G < SH) {
+        y_fwd_mf<N, E, PREC, NSG, G, SH>(v, j, tabs, lds, ls, A, sc);
+        y_fwd_mf_groups<N, E, PREC, NSG, G + NSG, SH>(v, j, tabs, lds, ls, A, sc);
+    }
+}
+template <int N, int E, int PREC, int NSG, int G, int SH>
+__device__ __forceinline__ void y_inv_mf_groups(float2 (&v)[SH][E], int j, const float2* tabs, float2* lds, int ls,
+                                                const MfDft<PREC>& A, const MfScales& sc, float2* __restrict__ dst0,
+                                                int ny, float osc) {
+    if constexpr (G < SH) {
+        y_inv_mf_store<N, E, PREC, NSG, G, SH>(v, j, tabs, lds, ls, A, sc, dst0, ny, osc);
+        y_inv_mf_groups<N, E, PREC, NSG, G + NSG, SH>(v, j, tabs, lds, ls, A, sc, dst0, ny, osc);
+    }
+}
+
+// ---------------------------------------------------------------------
 // y pass with two thread sets (even NZ, E = 8 for NZ <= 4 and 4 above, T =
 // PY/E in [64, 256], 2T <= 512 threads): set g < 2 transforms signals
 // [g*S/2, (g+1)*S/2), so a thread holds half the signals of its E bins; for
@@ -674,10 +1005,12 @@ __device__ __forceinline__ void y_swap(float2 (&v)[SH][E], int g, int j, float2*
     }
 }
 
-template <int NZ, int PY, bool BAT>
+// PREC 0: FP32 transforms on the vector units; 1, 2: split BF16 / FP16 radix-16
+// stages on the matrix cores (kmax: largest magnitude in K, for the FP16 scales).
+template <int NZ, int PY, bool BAT, int PREC>
 __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, const ChainDesc* __restrict__ dl,
                                                    const float* __restrict__ K,
-                                                   const float2* __restrict__ tw) {
+                                                   const float2* __restrict__ tw, float kmax) {
     const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
     const SweepArgs a = cd.a;
     float2* __restrict__ X = cd.X;
@@ -698,10 +1031,45 @@ __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, cons
             v[s][q] = (q < QH && y < ny) ? src[y] : make_float2(0.f, 0.f);
         }
     }
-    build_twiddles<PY, E, 2 * T>(twl, tw);
-    __syncthreads();
     float2* mine = lds + g * NSG * LS;
-    y_groups<PY, E, false, NSG, 0, SH>(v, j, twl, mine, LS);
+    [[maybe_unused]] MfScales msc{1.f, 1.f, 1.f};
+    if constexpr (PREC == 0) {
+        build_twiddles<PY, E, 2 * T>(twl, tw);
+        __syncthreads();
+        y_groups<PY, E, false, NSG, 0, SH>(v, j, twl, mine, LS);
+    } else {
+        mf_build_twiddles<PY, E, 2 * T, PREC>(twl, tw);
+        if constexpr (PREC == 2) {
+            // the block's largest input magnitude bounds every pass's inputs:
+            // forward pass 1 (after the radix-E pass over E/2 nonzero points)
+            // E/2 * xmax, pass 2 16 times that; inverse pass 1 the mixed
+            // spectrum, |H| <= 3 NZ kmax * ny xmax (twice that for the paired
+            // kx = 0 block), pass 2 16 times that
+            float mx = 0.f;
+#pragma unroll
+            for (int s = 0; s < SH; ++s)
+#pragma unroll
+                for (int q = 0; q < QH; ++q) mx = fmaxf(mx, fmaxf(fabsf(v[s][q].x), fabsf(v[s][q].y)));
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+            float* red = (float*)(twl + mf_tw_len(PY, E));
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+            __syncthreads();
+            mx = 0.f;
+#pragma unroll
+            for (int w = 0; w < 2 * T / 64; ++w) mx = fmaxf(mx, red[w]);
+            const float bf = 0.5f * E * mx, bi = 2.0f * 3.0f * NZ * kmax * (float)ny * mx;
+            constexpr float DF = mf_kf(PY, E) >= 2 ? 16.0f : 1.0f, DI = mf_ki(PY, E) >= 2 ? 16.0f : 1.0f;
+            const float f1 = mf_scale(bf), i1 = mf_scale(bi);
+            msc.f1 = f1;
+            msc.i1 = i1 * DF / f1;        // forward result carries f1 / DF
+            msc.out = DI / i1;            // inverse result carries i1 / DI
+        } else {
+            __syncthreads();
+        }
+        const MfDft<PREC> A = mf_dft16<PREC, false>(threadIdx.x & 63, tw);
+        y_fwd_mf_groups<PY, E, PREC, NSG, 0, SH>(v, j, twl, mine, LS, A, msc);
+    }
     if (kx == 0) y_pair<PY, E, true, NSG, 0, SH>(v, j, mine, LS);
     y_swap<E, T, NSG, SH, 0>(v, g, j, lds);
     // signal s' of bin i: s' < SH ? v[s'][i] : v[s' - SH][i + HB]
@@ -792,7 +1160,35 @@ __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, cons
     if (kx == 0) y_pair<PY, E, false, NSG, 0, SH>(v, j, mine, LS);
     // inverse transforms group by group, each group's outputs stored as soon
     // as they are final (the stores overlap the next group's transforms)
-    y_inv_store<PY, E, NSG, 0, SH, QH>(v, j, twl, mine, LS, X + ((long long)kx * S + g * SH) * ny, ny);
+    if constexpr (PREC == 0) {
+        y_inv_store<PY, E, NSG, 0, SH, QH>(v, j, twl, mine, LS, X + ((long long)kx * S + g * SH) * ny, ny);
+    } else {
+        const MfDft<PREC> Ai = mf_dft16<PREC, true>(threadIdx.x & 63, tw);
+        y_inv_mf_groups<PY, E, PREC, NSG, 0, SH>(v, j, twl, mine, LS, Ai, msc, X + ((long long)kx * S + g * SH) * ny,
+                                                 ny, msc.out);
+    }
+}
+
+// Shapes whose y pass can run split-precision stages: the two-set kernel
+// with whole waves per set and at least one radix-16 stage each way.
+constexpr bool ysplit_ok(int nz, int Py) {
+    return y2_use(nz, Py) && Py / y2_E(nz) >= 64 && mf_kf(Py, y2_E(nz)) >= 1 && mf_rf(Py, y2_E(nz)) <= y2_E(nz) &&
+           mf_ri(Py, y2_E(nz)) <= y2_E(nz);
+}
+
+template <int NZ, int PY, int PREC>
+hipError_t launch_ypass2(const Chains& c, const DemagPlan& p, const float2* tw, hipStream_t s) {
+    constexpr int E2 = y2_E(NZ);
+    constexpr size_t sh = PREC == 0 ? sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + tw_len(PY, E2))
+                                    : sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + mf_tw_len(PY, E2)) +
+                                          sizeof(float) * 16;
+    if (c.many)
+        hipLaunchKernelGGL((k_ypass2<NZ, PY, true, PREC>), dim3(p.L, c.n), dim3(2 * PY / E2), sh, s, c.one, c.many,
+                           (const float*)p.K, tw, p.kmax);
+    else
+        hipLaunchKernelGGL((k_ypass2<NZ, PY, false, PREC>), dim3(p.L), dim3(2 * PY / E2), sh, s, c.one, c.many,
+                           (const float*)p.K, tw, p.kmax);
+    return hipGetLastError();
 }
 
 // y-pass launcher for one layer count (instantiated per NZ in its own unit).
@@ -800,16 +1196,17 @@ template <int NZ, int PY>
 hipError_t launch_ypass_py(const Chains& c, const DemagPlan& p, const float2* tw, hipStream_t s) {
     constexpr int E = y_E(NZ, PY);
     if constexpr (y2_use(NZ, PY)) {
-        constexpr int E2 = y2_E(NZ);
-        constexpr size_t sh = sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + tw_len(PY, E2));
-        if (c.many)
-            hipLaunchKernelGGL((k_ypass2<NZ, PY, true>), dim3(p.L, c.n), dim3(2 * PY / E2), sh, s, c.one, c.many,
-                               (const float*)p.K, tw);
-        else
-            hipLaunchKernelGGL((k_ypass2<NZ, PY, false>), dim3(p.L), dim3(2 * PY / E2), sh, s, c.one, c.many,
-                               (const float*)p.K, tw);
-        return hipGetLastError();
+        if (p.prec != 0) {
+            if constexpr (ysplit_ok(NZ, PY)) {
+                if (p.prec == 1) return launch_ypass2<NZ, PY, 1>(c, p, tw, s);
+                return launch_ypass2<NZ, PY, 2>(c, p, tw, s);
+            } else {
+                return hipErrorInvalidValue;   // rejected at context creation
+            }
+        }
+        return launch_ypass2<NZ, PY, 0>(c, p, tw, s);
     } else if constexpr (3 * NZ * E <= 96) {
+        if (p.prec != 0) return hipErrorInvalidValue;   // rejected at context creation
         constexpr size_t sh = sizeof(float2) * (y_NSG(NZ, PY) * lds_len(PY) + tw_len(PY, E));
         if (c.many)
             hipLaunchKernelGGL((k_ypass<NZ, PY, true>), dim3(p.L, c.n), dim3(PY / E), sh, s, c.one, c.many,

@@ -87,6 +87,8 @@ struct DemagPlan {
     int logL, logPy;
     float2* X;        // [(L+1)][S][ny] complex work buffer
     float* K;         // tensor spectrum
+    int prec;         // y-pass DFT stages: 0 FP32 (vector units), 1 split BF16, 2 split FP16 (matrix cores)
+    float kmax;       // largest magnitude in K (bounds for the FP16 scales)
 };
 // Everything a sweep-path kernel needs from one chain.  A single chain's is
 // passed by value; for a batch the descriptors of chains of one shape (grid,
@@ -120,6 +122,7 @@ __device__ __forceinline__ const ChainDesc& chain_at(const ChainDesc& one, const
 }
 
 int ypass_E(int nz, int Py);                    // elements per thread of the y pass
+bool ypass_split_ok(int nz, int Py);            // split-precision y-pass stages available for this shape
 hipError_t launch_init(const SweepArgs& a, const ClassCoef* ctab, const uint32_t* cid, float* m, int kind,
                        float dx, float dy, float dz, hipStream_t s);
 hipError_t launch_to_split(const SweepArgs& a, const float* nat, float* split, hipStream_t s);

@@ -16,7 +16,9 @@ SO = os.path.join(HERE, "libmmc.so")
 MMC_OK, MMC_ERR_ARG, MMC_ERR_DOMAIN, MMC_ERR_OOM, MMC_ERR_DEVICE, MMC_ERR_STATE, MMC_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MMC_MF_LANGEVIN, MMC_MF_BRILLOUIN_HALF = 0, 1
 MMC_LEN_PAPER, MMC_LEN_EXACT = 0, 1
-MMC_DEMAG_OFF, MMC_DEMAG_FP32 = 0, 1
+MMC_DEMAG_OFF, MMC_DEMAG_FP32, MMC_DEMAG_SPLIT_BF16, MMC_DEMAG_SPLIT_FP16 = 0, 1, 2, 3
+_DEMAG_MODES = {False: MMC_DEMAG_OFF, True: MMC_DEMAG_FP32, "off": MMC_DEMAG_OFF, "fp32": MMC_DEMAG_FP32,
+                "split_bf16": MMC_DEMAG_SPLIT_BF16, "split_fp16": MMC_DEMAG_SPLIT_FP16}
 MMC_ANIS_UNIAXIAL, MMC_ANIS_CUBIC = 0, 1
 MUB = 9.2740100783e-24
 
@@ -142,7 +144,7 @@ class Chain:
                            mu_atomic=float(mu), mf=int(mf))
         run = mmc_run(seed=int(seed), chain_id=int(chain_id), cone_deg=int(cone_deg), adapt_every=int(adapt_every),
                       sigma_fixed=float(sigma_fixed), lenmove=int(lenmove),
-                      demag=MMC_DEMAG_FP32 if demag else MMC_DEMAG_OFF, refresh_per_sweep=int(refresh_per_sweep),
+                      demag=_DEMAG_MODES[demag], refresh_per_sweep=int(refresh_per_sweep),
                       T=float(T), B=(C.c_double * 3)(*[float(v) for v in B]), init=int(init),
                       init_dir=(C.c_double * 3)(*[float(v) for v in init_dir]))
         if stream == "torch":

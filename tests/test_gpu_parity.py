@@ -294,3 +294,44 @@ def test_uniaxial_temperature_law(O, mmc):
     assert abs(terms[2] - Eo[2]) < 1e-5 * abs(Eo[2]), (terms[2], Eo[2])
     unscaled = O.System(grid, cell, **kw).energy(m0.astype(np.float64))[2]
     assert abs(Eo[2]) < 0.5 * abs(unscaled)         # me < 1: the law lowers the anisotropy
+
+
+# Split-precision y-direction DFT stages (matrix cores, hi + lo products in FP32):
+# every shape class the split path supports (padded y lengths 256 .. 2048, two
+# and one radix-16 stages each way, even layer counts 2 .. 8)
+SPLIT_GRIDS = [((64, 200, 2), (5e-9,) * 3), ((48, 300, 2), (5e-9, 4e-9, 3e-9)), ((64, 520, 4), (5e-9,) * 3),
+               ((40, 100, 8), (3e-9,) * 3), ((16, 300, 8), (2e-9,) * 3), ((24, 400, 6), (4e-9, 3e-9, 2e-9)),
+               ((256, 256, 2), (5e-9,) * 3), ((300, 270, 4), (3e-9,) * 3)]
+# relative L2 error bars against the FP64 oracle: 1e-3 for split BF16 (16
+# significant bits per operand); split FP16 keeps 22 bits per operand and
+# is held to the FP32 bar
+SPLIT_TOL = {"split_bf16": 1e-3, "split_fp16": 1e-5}
+
+
+@pytest.mark.parametrize("mode", ["split_bf16", "split_fp16"])
+@pytest.mark.parametrize("grid,cell", SPLIT_GRIDS)
+def test_demag_field_split_matches_oracle(O, mmc, grid, cell, mode):
+    N = int(np.prod(grid))
+    ch = mmc.Chain(grid, cell, T=300.0, demag=mode, **MAT)
+    m = workloads.random_state(N, seed=N + 1)
+    ch.set_m(m)
+    h = ch.demag_field().astype(np.float64)
+    ref = O.DemagPlan(grid, cell)(m.astype(np.float64))
+    rel = np.linalg.norm(h - ref) / np.linalg.norm(ref)
+    # also a nearly uniform state: large low-frequency bins, small others
+    mu = workloads.perturbed_uniform_state(N, seed=4, L=0.9, spread=0.05)
+    ch.set_m(mu)
+    hu = ch.demag_field().astype(np.float64)
+    refu = O.DemagPlan(grid, cell)(mu.astype(np.float64))
+    relu = np.linalg.norm(hu - refu) / np.linalg.norm(refu)
+    print(grid, mode, "rel L2 %.2e (random), %.2e (near uniform)" % (rel, relu))
+    assert rel < SPLIT_TOL[mode] and relu < SPLIT_TOL[mode]
+    ch.close()
+
+
+def test_demag_split_rejects_unsupported_shapes(mmc):
+    # odd layer count, padded y too short, and nz 8 with a 512-point y transform
+    for grid in [(64, 300, 3), (64, 100, 2), (40, 200, 8)]:
+        with pytest.raises(mmc.MMCError) as ei:
+            mmc.Chain(grid, (5e-9,) * 3, T=300.0, demag="split_bf16", **MAT)
+        assert ei.value.status == mmc.MMC_ERR_UNSUPPORTED
