@@ -284,6 +284,19 @@ mmc_status mmc_get_stats(mmc_ctx* ctx, mmc_stats* out);
  * their count, and resets the accumulators. */
 mmc_status mmc_take_averages(mmc_ctx* ctx, double avg_out[4], uint64_t* n_out);
 
+/* Tile shape of the demag x passes, tuned by the library at mmc_create: the
+ * forward and inverse x transforms run with 1, 2 or 4 rows per thread (tiles
+ * of 1-4 rows per group of threads that transforms one row); each candidate
+ * is timed on the chain's own buffers, the fastest is kept (every candidate
+ * gives the same bits) and the choice is cached for the process per (padded x
+ * length, ny, nz).  MMC_TUNE=0 in the environment keeps the untuned default.
+ * Returns the chosen rows per thread (forward, inverse) and, when
+ * us_per_launch is not NULL, the measured microseconds per launch of the
+ * candidates (forward 1, 2, 4, inverse 1, 2, 4; zeros when not tuned).
+ * MMC_TUNE=1, 2 or 4 forces that many rows per thread in both directions.
+ * Errors: MMC_ERR_STATE without demag. */
+mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_per_launch[6]);
+
 /* Run state for checkpoint/resume: the sweep counter, cone angle and accept
  * window; with the state m (mmc_get_m / mmc_set_m) this restores a chain
  * bit-exactly (the generator is stateless).  get synchronises the stream;
@@ -308,8 +321,38 @@ mmc_status mmc_set_state(mmc_ctx* ctx, uint64_t sweep, int32_t cone_deg, uint64_
  * device error), MMC_ERR_DEVICE / MMC_ERR_OOM from HIP. */
 mmc_status mmc_batch_create(mmc_ctx* const* chains, int32_t n, mmc_batch** out);
 mmc_status mmc_batch_sweep(mmc_batch* batch, int32_t n);
+/* Synchronises the first chain's stream; MMC_ERR_DEVICE (and every chain of
+ * the batch unusable) if a persistent launch raised its error flag. */
 mmc_status mmc_batch_sync(mmc_batch* batch);
 void mmc_batch_destroy(mmc_batch* batch);
+
+/* How a batch's sweeps are scheduled (the results are the same bits in every
+ * form: each is the single-chain sequence of kernels per chain).  In this
+ * build the persistent form is switched off (its launches did not finish on
+ * the GPU): requesting it gives MMC_ERR_UNSUPPORTED and MMC_SCHED_AUTO runs
+ * the grouped form without trials.
+ *   MMC_SCHED_GROUPS: chains of one shape share each launch of the
+ *     single-chain sequence, shape groups on streams of their own, the whole
+ *     captured as one HIP graph;
+ *   MMC_SCHED_PERSISTENT: one persistent kernel per mmc_batch_sweep call
+ *     (graph-captured with the reset of its counters) advances every chain:
+ *     its blocks take work items (sweep, stage of the sweep, chain, tile) from
+ *     a global counter and wait on per-chain completion counts, so small and
+ *     large chains, temperatures and fields interleave in one launch.  It
+ *     serves chains of uniform material without DMI, with demag off or FP32
+ *     with nz 1 or 2, 17 <= nx <= 1024 and 17 <= ny <= 512, and one
+ *     length-move kind across the batch (else MMC_ERR_UNSUPPORTED).  A wait
+ *     that exceeds 5 s raises an error flag that mmc_batch_sync reports;
+ *   MMC_SCHED_AUTO (default): on the first mmc_batch_sweep the library times
+ *     three sweeps of each form that serves the chains, from the same state
+ *     (restored afterwards, so the chains continue bit for bit), keeps the
+ *     faster and caches the choice for batches of the same chain shapes.
+ * set: the choice applies from the next mmc_batch_sweep.  get: the form in
+ * use (MMC_SCHED_GROUPS before the first sweep under AUTO) and the trial
+ * times in ms (groups, persistent; 0 when not timed); trial_ms may be NULL. */
+typedef enum { MMC_SCHED_AUTO = 0, MMC_SCHED_GROUPS = 1, MMC_SCHED_PERSISTENT = 2 } mmc_sched;
+mmc_status mmc_batch_set_schedule(mmc_batch* batch, int32_t sched);
+mmc_status mmc_batch_get_schedule(mmc_batch* batch, int32_t* used, double trial_ms[2]);
 
 /* Synchronise the context's stream. */
 mmc_status mmc_sync(mmc_ctx* ctx);

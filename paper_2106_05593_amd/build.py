@@ -10,7 +10,7 @@ SO = os.path.join(HERE, "libmmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (source, extra defines, object name); the y pass is compiled once per layer count
 UNITS = [("csrc/api.cpp", [], "api.o"), ("csrc/setup.cpp", [], "setup.o"), ("csrc/kernels.hip", [], "kernels.o"), ("csrc/sweep.hip", [], "sweep.o"),
-         ("csrc/demag.hip", [], "demag.o")] + \
+         ("csrc/demag.hip", [], "demag.o"), ("csrc/persist.hip", [], "persist.o")] + \
         [("csrc/ypass.hip", ["-DMMC_NZ=%d" % k], "ypass_nz%d.o" % k) for k in range(1, 9)]
 
 

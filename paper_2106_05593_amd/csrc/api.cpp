@@ -5,7 +5,11 @@
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
+#include <chrono>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -86,6 +90,7 @@ struct mmc_ctx {
     // demag
     bool demag = false;
     DemagPlan plan{};
+    double xtune_us[6] = {0, 0, 0, 0, 0, 0};   // x-pass tuning: us per launch of each candidate
     float2* d_tw = nullptr;
     SweepArgs args{};
     unsigned long long host_sweep = 0;
@@ -110,8 +115,20 @@ struct mmc_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_n = -1;
+    int graph_sched = -1;
     std::vector<unsigned> versions;
+    // schedule: requested (MMC_SCHED_*) and in use; persistent plan
+    int sched_req = MMC_SCHED_AUTO;
+    int sched_used = MMC_SCHED_GROUPS;
+    bool tuned = false;                   // the automatic choice was made for these chains
+    double tune_ms[2] = {0.0, 0.0};       // measured time per trial for groups, persistent (0: not timed)
+    PersistPlan pplan;
+    bool pplan_ok = false;
 };
+
+// Automatic schedule choices by batch signature (process-wide).
+static std::mutex g_sched_mu;
+static std::map<std::string, int> g_sched_cache;
 
 static void update_args(mmc_ctx* c) {
     SweepArgs& a = c->args;
@@ -229,6 +246,83 @@ static mmc_status enqueue_sweeps(mmc_ctx* ctx, int n, double* series, unsigned l
     mmc_status s = enqueue_core(ctx, single(ctx), n, ctx->stream, series, rec_base, prof);
     if (s != MMC_OK) return s;
     ctx->host_sweep += (unsigned long long)n;
+    return MMC_OK;
+}
+
+// ---------------------------------------------------------------------
+// Tile-shape tuner of the x passes: rows per thread 1, 2 or 4 (tiles of
+// x_rows_conc(L) * rpt rows), timed for each direction on the chain's own
+// buffers (the x passes write only the spectrum work buffer and the demag
+// field, both recomputed before every use, and every choice gives the same
+// bits), the fastest kept; the choice is cached per (x length, ny, nz).
+// MMC_TUNE=0 in the environment keeps the untuned default.
+// ---------------------------------------------------------------------
+struct XTune {
+    int f = 2, i = 2;
+    double us[6] = {0, 0, 0, 0, 0, 0};   // forward rpt 1, 2, 4; inverse rpt 1, 2, 4 (us per launch)
+};
+static std::mutex g_xtune_mu;
+static std::map<std::string, XTune> g_xtune;
+
+static mmc_status tune_x(mmc_ctx* ctx) {
+    DemagPlan& p = ctx->plan;
+    std::fill(ctx->xtune_us, ctx->xtune_us + 6, 0.0);
+    const char* env = getenv("MMC_TUNE");
+    if (env && (env[0] == '0' || env[0] == '1' || env[0] == '2' || env[0] == '4') && env[1] == 0) {
+        // 0: the untuned default; 1, 2, 4: that many rows per thread both ways
+        p.rpt_f = p.rpt_i = env[0] == '0' ? x_rpt_default(p.L) : env[0] - '0';
+        return MMC_OK;
+    }
+    char key[64];
+    snprintf(key, sizeof key, "%d,%d,%d", p.L, ctx->g.ny, ctx->g.nz);
+    {
+        std::lock_guard<std::mutex> lk(g_xtune_mu);
+        auto it = g_xtune.find(key);
+        if (it != g_xtune.end()) {
+            p.rpt_f = it->second.f;
+            p.rpt_i = it->second.i;
+            std::copy(it->second.us, it->second.us + 6, ctx->xtune_us);
+            return MMC_OK;
+        }
+    }
+    p.rpt_f = p.rpt_i = x_rpt_default(p.L);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(MMC_ERR_DEVICE, "event creation failed");
+    }
+    XTune t;
+    const int rpts[3] = {1, 2, 4};
+    constexpr int kWarm = 2, kTimed = 5;
+    mmc_status st = MMC_OK;
+    for (int d = 0; d < 2 && st == MMC_OK; ++d) {
+        const int stage = d == 0 ? 0 : 2;
+        double best = 1e30;
+        for (int r = 0; r < 3 && st == MMC_OK; ++r) {
+            (d == 0 ? p.rpt_f : p.rpt_i) = rpts[r];
+            hipError_t e = hipSuccess;
+            for (int k = 0; k < kWarm + kTimed && e == hipSuccess; ++k) {
+                if (k == kWarm) e = hipEventRecord(e0, ctx->stream);
+                if (e == hipSuccess) e = launch_demag_stage(stage, ctx->args, p, single(ctx), 3, ctx->d_tw, ctx->stream);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { st = fail(MMC_ERR_DEVICE, "x-pass tuning: %s", hipGetErrorString(e)); break; }
+            const double us = 1e3 * ms / kTimed;
+            t.us[3 * d + r] = us;
+            if (us < best) { best = us; (d == 0 ? t.f : t.i) = rpts[r]; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MMC_OK) return st;
+    p.rpt_f = t.f;
+    p.rpt_i = t.i;
+    std::copy(t.us, t.us + 6, ctx->xtune_us);
+    std::lock_guard<std::mutex> lk(g_xtune_mu);
+    g_xtune[key] = t;
     return MMC_OK;
 }
 
@@ -389,6 +483,7 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
                 hipStreamSynchronize(ctx->stream) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "twiddle tables"); break; }
         }
         st = init_state(ctx);
+        if (st == MMC_OK && ctx->demag) st = tune_x(ctx);
     } while (false);
     if (st != MMC_OK) {
         mmc_destroy(ctx);
@@ -686,6 +781,17 @@ mmc_status mmc_subsweep(mmc_ctx* ctx, int32_t colour, const float* h_in, uint8_t
     return MMC_OK;
 }
 
+mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_per_launch[6]) {
+    mmc_status s = check_live(ctx);
+    if (s != MMC_OK) return s;
+    if (!rows_per_thread) return fail(MMC_ERR_ARG, "NULL output");
+    if (!ctx->demag) return fail(MMC_ERR_STATE, "demag is off for this context");
+    rows_per_thread[0] = ctx->plan.rpt_f;
+    rows_per_thread[1] = ctx->plan.rpt_i;
+    if (us_per_launch) std::copy(ctx->xtune_us, ctx->xtune_us + 6, us_per_launch);
+    return MMC_OK;
+}
+
 mmc_status mmc_get_stats(mmc_ctx* ctx, mmc_stats* out) {
     mmc_status s = check_live(ctx);
     if (s != MMC_OK) return s;
@@ -794,6 +900,7 @@ static void batch_drop_graph(mmc_batch* b) {
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_n = -1;
+    b->graph_sched = -1;
 }
 
 static bool same_shape(const mmc_ctx* a, const mmc_ctx* c) {
@@ -833,24 +940,90 @@ static mmc_status batch_regroup(mmc_batch* b) {
     return MMC_OK;
 }
 
-mmc_status mmc_batch_sweep(mmc_batch* b, int32_t n) {
+// The persistent schedule is switched off: its launches did not finish on
+// the GPU and the cause is not found yet.  Requests for it are refused and the
+// automatic choice is the grouped form.
+static constexpr bool kPersistEnabled = false;
+
+// The persistent kernel serves uniform materials without DMI, FP32 or no
+// demag with 1 or 2 layers, and one length-move kind across the batch.
+static bool batch_persist_ok(const mmc_batch* b) {
+    if (!kPersistEnabled) return false;
+    for (const mmc_ctx* c : b->ch) {
+        if (c->has_classes || c->cubic || c->mat.D0 != 0.0) return false;
+        if (c->run.demag != MMC_DEMAG_OFF && c->run.demag != MMC_DEMAG_FP32) return false;
+        if (c->run.lenmove != b->ch[0]->run.lenmove) return false;
+        if (!persist_shape_ok(c->g.nx, c->g.ny, c->g.nz, c->demag)) return false;
+    }
+    return true;
+}
+
+static std::string batch_signature(const mmc_batch* b) {
+    std::vector<std::string> parts;
+    char buf[160];
+    for (const mmc_ctx* c : b->ch) {
+        snprintf(buf, sizeof buf, "%d,%d,%d,%.6g,%.6g,%.6g,%d,%d,%d", c->g.nx, c->g.ny, c->g.nz, c->cs.hx, c->cs.hy,
+                 c->cs.hz, c->run.demag, c->run.refresh_per_sweep, c->run.lenmove);
+        parts.push_back(buf);
+    }
+    std::sort(parts.begin(), parts.end());
+    std::string sig;
+    for (auto& p : parts) sig += p + ";";
+    return sig;
+}
+
+static mmc_status batch_build_persist(mmc_batch* b) {
     mmc_ctx* ctx = nullptr;
-    if (!b) return fail(MMC_ERR_ARG, "NULL batch");
-    if (n < 0) return fail(MMC_ERR_ARG, "negative sweep count");
-    if (n == 0) return MMC_OK;
-    for (auto* c : b->ch)
-        if (c->dead) return fail(MMC_ERR_STATE, "a chain had a device error");
-    HIPCK(hipSetDevice(b->ch[0]->device));
-    bool stale = b->graph_n != n || b->versions.size() != b->ch.size();
-    for (size_t i = 0; !stale && i < b->ch.size(); ++i) stale = b->versions[i] != b->ch[i]->version;
+    if (b->pplan_ok) return MMC_OK;
+    std::vector<PersistChain> pcs(b->ch.size());
+    for (size_t i = 0; i < b->ch.size(); ++i) {
+        const mmc_ctx* c = b->ch[i];
+        PersistChain& q = pcs[i];
+        q.cd = make_desc(c);
+        q.K = c->plan.K;
+        q.tw = c->d_tw;
+        q.L = c->plan.L;
+        q.Py = c->plan.Py;
+        q.demag = c->demag;
+        q.refresh_per_sweep = c->run.refresh_per_sweep;
+        q.shift = c->fp_shift;
+    }
+    b->pplan.exact = b->ch[0]->run.lenmove == MMC_LEN_EXACT;
+    const hipError_t e = persist_build(pcs.data(), (int)pcs.size(), &b->pplan);
+    if (e != hipSuccess) {
+        persist_free(&b->pplan);
+        return fail(MMC_ERR_DEVICE, "persistent plan: %s", hipGetErrorString(e));
+    }
+    HIPCK(hipMemset(b->pplan.err, 0, sizeof(int)));
+    b->pplan_ok = true;
+    return MMC_OK;
+}
+
+// Time limit of one wait in the persistent kernel (s): far above any phase.
+static constexpr double kPersistWaitLimit = 5.0;
+
+// Captures n sweeps of every chain under schedule sched as one graph on the
+// first chain's stream.
+static mmc_status batch_capture(mmc_batch* b, int n, int sched) {
+    mmc_ctx* ctx = nullptr;
+    batch_drop_graph(b);
+    // a chain's own stream may hold earlier work: order it before the graph
+    for (auto* c : b->ch) HIPCK(hipStreamSynchronize(c->stream));
+    mmc_status st = MMC_OK;
+    if (sched == MMC_SCHED_PERSISTENT) {
+        // descriptors change with T, field or grains: rebuild the plan
+        if (b->pplan_ok) { persist_free(&b->pplan); b->pplan_ok = false; }
+        st = batch_build_persist(b);
+    } else {
+        st = batch_regroup(b);
+    }
+    if (st != MMC_OK) return st;
     hipStream_t s0 = b->ch[0]->stream;
-    if (stale) {
-        batch_drop_graph(b);
-        // a chain's own stream may hold earlier work: order it before the graph
-        for (auto* c : b->ch) HIPCK(hipStreamSynchronize(c->stream));
-        mmc_status st = batch_regroup(b);
-        if (st != MMC_OK) return st;
-        HIPCK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    HIPCK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    if (sched == MMC_SCHED_PERSISTENT) {
+        const hipError_t e = persist_launch(b->pplan, n, kPersistWaitLimit, s0);
+        if (e != hipSuccess) st = fail(MMC_ERR_DEVICE, "persistent launch: %s", hipGetErrorString(e));
+    } else {
         HIPCK(hipEventRecord(b->fork, s0));
         for (size_t gi = 0; gi < b->groups.size() && st == MMC_OK; ++gi) {
             const BatchGroup& g = b->groups[gi];
@@ -862,15 +1035,160 @@ mmc_status mmc_batch_sweep(mmc_batch* b, int32_t n) {
             HIPCK(hipEventRecord(b->done[gi], b->streams[gi]));
             HIPCK(hipStreamWaitEvent(s0, b->done[gi], 0));
         }
-        hipGraph_t gr = nullptr;
-        hipError_t e = hipStreamEndCapture(s0, &gr);
-        if (st != MMC_OK) { if (gr) (void)hipGraphDestroy(gr); return st; }
-        HIPCK(e);
-        b->graph = gr;
-        HIPCK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-        b->graph_n = n;
-        b->versions.resize(b->ch.size());
-        for (size_t i = 0; i < b->ch.size(); ++i) b->versions[i] = b->ch[i]->version;
+    }
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(s0, &gr);
+    if (st != MMC_OK) { if (gr) (void)hipGraphDestroy(gr); return st; }
+    HIPCK(e);
+    b->graph = gr;
+    HIPCK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_n = n;
+    b->graph_sched = sched;
+    b->versions.resize(b->ch.size());
+    for (size_t i = 0; i < b->ch.size(); ++i) b->versions[i] = b->ch[i]->version;
+    return MMC_OK;
+}
+
+// State of the chains (m, run state, statistics accumulators) for trial runs.
+struct BatchSnapshot {
+    std::vector<void*> buf;
+};
+static mmc_status batch_snapshot(mmc_batch* b, BatchSnapshot& sn, bool restore) {
+    mmc_ctx* ctx = nullptr;
+    if (!restore) sn.buf.assign(b->ch.size(), nullptr);
+    for (size_t i = 0; i < b->ch.size(); ++i) {
+        const mmc_ctx* c = b->ch[i];
+        const size_t mb = sizeof(float) * 6 * (size_t)c->Nc;
+        const size_t tot = mb + sizeof(DevState) + sizeof(SweepAccum);
+        if (!restore) HIPCK(hipMalloc(&sn.buf[i], tot));
+        char* p = (char*)sn.buf[i];
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        if (restore) {
+            HIPCK(hipMemcpy(c->d_m, p, mb, k));
+            HIPCK(hipMemcpy(c->d_st, p + mb, sizeof(DevState), k));
+            HIPCK(hipMemcpy(c->d_acc, p + mb + sizeof(DevState), sizeof(SweepAccum), k));
+        } else {
+            HIPCK(hipMemcpy(p, c->d_m, mb, k));
+            HIPCK(hipMemcpy(p + mb, c->d_st, sizeof(DevState), k));
+            HIPCK(hipMemcpy(p + mb + sizeof(DevState), c->d_acc, sizeof(SweepAccum), k));
+        }
+    }
+    return MMC_OK;
+}
+static void batch_snapshot_free(BatchSnapshot& sn) {
+    for (void* p : sn.buf) if (p) (void)hipFree(p);
+    sn.buf.clear();
+}
+
+// Automatic schedule: times a few sweeps of each form from the same state
+// (which is restored afterwards, so the chains continue bit for bit) and keeps
+// the faster; the choice is cached per batch signature.
+static mmc_status batch_tune(mmc_batch* b) {
+    mmc_ctx* ctx = nullptr;
+    const std::string sig = batch_signature(b);
+    {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        auto it = g_sched_cache.find(sig);
+        if (it != g_sched_cache.end()) { b->sched_used = it->second; b->tuned = true; return MMC_OK; }
+    }
+    constexpr int kTrial = 3;
+    for (auto* c : b->ch) HIPCK(hipStreamSynchronize(c->stream));
+    BatchSnapshot sn;
+    mmc_status st = batch_snapshot(b, sn, false);
+    hipStream_t s0 = b->ch[0]->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == MMC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = fail(MMC_ERR_DEVICE, "event creation failed");
+    for (int sched = MMC_SCHED_GROUPS; st == MMC_OK && sched <= MMC_SCHED_PERSISTENT; ++sched) {
+        st = batch_capture(b, kTrial, sched);
+        for (int rep = 0; st == MMC_OK && rep < 2; ++rep) {   // warm-up, then timed
+            if (hipEventRecord(e0, s0) != hipSuccess || hipGraphLaunch(b->exec, s0) != hipSuccess ||
+                hipEventRecord(e1, s0) != hipSuccess || hipStreamSynchronize(s0) != hipSuccess) {
+                st = fail(MMC_ERR_DEVICE, "trial launch failed");
+                break;
+            }
+            if (sched == MMC_SCHED_PERSISTENT) {
+                int err = 0;
+                if (hipMemcpy(&err, b->pplan.err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess || err)
+                    st = fail(MMC_ERR_DEVICE, "persistent trial: a wait exceeded its time limit");
+            }
+            float ms = 0.f;
+            if (st == MMC_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+            b->tune_ms[sched - 1] = ms;
+            if (st == MMC_OK) st = batch_snapshot(b, sn, true);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    batch_snapshot_free(sn);
+    batch_drop_graph(b);
+    if (st != MMC_OK) {
+        for (auto* c : b->ch) c->dead = true;
+        return st;
+    }
+    b->sched_used = b->tune_ms[1] < b->tune_ms[0] ? MMC_SCHED_PERSISTENT : MMC_SCHED_GROUPS;
+    b->tuned = true;
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    g_sched_cache[sig] = b->sched_used;
+    return MMC_OK;
+}
+
+mmc_status mmc_batch_set_schedule(mmc_batch* b, int32_t sched) {
+    mmc_ctx* ctx = nullptr;
+    if (!b) return fail(MMC_ERR_ARG, "NULL batch");
+    if (sched < MMC_SCHED_AUTO || sched > MMC_SCHED_PERSISTENT) return fail(MMC_ERR_ARG, "unknown schedule %d", sched);
+    HIPCK(hipSetDevice(b->ch[0]->device));
+    if (sched == MMC_SCHED_PERSISTENT && !kPersistEnabled)
+        return fail(MMC_ERR_UNSUPPORTED, "the persistent schedule is switched off in this build");
+    if (sched == MMC_SCHED_PERSISTENT && !batch_persist_ok(b))
+        return fail(MMC_ERR_UNSUPPORTED,
+                    "persistent schedule needs uniform materials without DMI, FP32 or no demag with nz 1 or 2, "
+                    "x lengths 17..1024 and y lengths 17..512 with demag, and one length-move kind");
+    b->sched_req = sched;
+    b->tuned = false;
+    if (sched != MMC_SCHED_AUTO) b->sched_used = sched;
+    batch_drop_graph(b);
+    return MMC_OK;
+}
+
+mmc_status mmc_batch_get_schedule(mmc_batch* b, int32_t* used, double trial_ms[2]) {
+    mmc_ctx* ctx = nullptr;
+    if (!b || !used) return fail(MMC_ERR_ARG, "NULL argument");
+    *used = b->sched_used;
+    if (trial_ms) { trial_ms[0] = b->tune_ms[0]; trial_ms[1] = b->tune_ms[1]; }
+    return MMC_OK;
+}
+
+mmc_status mmc_batch_sweep(mmc_batch* b, int32_t n) {
+    mmc_ctx* ctx = nullptr;
+    if (!b) return fail(MMC_ERR_ARG, "NULL batch");
+    if (n < 0) return fail(MMC_ERR_ARG, "negative sweep count");
+    if (n == 0) return MMC_OK;
+    for (auto* c : b->ch)
+        if (c->dead) return fail(MMC_ERR_STATE, "a chain had a device error");
+    HIPCK(hipSetDevice(b->ch[0]->device));
+    // schedule: the requested one, or the tuned choice (groups when the
+    // persistent kernel does not serve these chains)
+    if (b->sched_req == MMC_SCHED_AUTO && !b->tuned) {
+        if (batch_persist_ok(b)) {
+            mmc_status st = batch_tune(b);
+            if (st != MMC_OK) return st;
+        } else {
+            b->sched_used = MMC_SCHED_GROUPS;
+            b->tuned = true;
+        }
+    }
+    if (b->sched_used == MMC_SCHED_PERSISTENT && !batch_persist_ok(b)) {
+        if (b->sched_req == MMC_SCHED_PERSISTENT)
+            return fail(MMC_ERR_UNSUPPORTED, "the chains no longer suit the persistent schedule");
+        b->sched_used = MMC_SCHED_GROUPS;
+    }
+    bool stale = b->graph_n != n || b->graph_sched != b->sched_used || b->versions.size() != b->ch.size();
+    for (size_t i = 0; !stale && i < b->ch.size(); ++i) stale = b->versions[i] != b->ch[i]->version;
+    hipStream_t s0 = b->ch[0]->stream;
+    if (stale) {
+        mmc_status st = batch_capture(b, n, b->sched_used);
+        if (st != MMC_OK) return st;
     }
     // work queued earlier on a chain's own stream (mmc_sweep, setters) runs
     // before the graph, and later work on that stream (getters, sweeps) after it
@@ -892,6 +1210,14 @@ mmc_status mmc_batch_sync(mmc_batch* b) {
     if (!b) return fail(MMC_ERR_ARG, "NULL batch");
     HIPCK(hipSetDevice(b->ch[0]->device));
     HIPCK(hipStreamSynchronize(b->ch[0]->stream));
+    if (b->pplan_ok) {
+        int err = 0;
+        HIPCK(hipMemcpy(&err, b->pplan.err, sizeof(int), hipMemcpyDeviceToHost));
+        if (err) {
+            for (auto* c : b->ch) c->dead = true;
+            return fail(MMC_ERR_DEVICE, "persistent batch: a wait exceeded its time limit; the chains are unusable");
+        }
+    }
     return MMC_OK;
 }
 
@@ -902,6 +1228,7 @@ void mmc_batch_destroy(mmc_batch* b) {
         (void)hipStreamSynchronize(b->ch[0]->stream);
     }
     batch_drop_graph(b);
+    if (b->pplan_ok) persist_free(&b->pplan);
     for (auto& g : b->groups) if (g.d_list) (void)hipFree(g.d_list);
     for (auto s : b->streams) if (s) (void)hipStreamDestroy(s);
     for (auto e : b->done) if (e) (void)hipEventDestroy(e);

@@ -16,33 +16,48 @@ extern template hipError_t launch_ypass_nz<7>(const Chains&, const DemagPlan&, c
 extern template hipError_t launch_ypass_nz<8>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
 
 int ypass_E(int nz, int Py) { return y_E(nz, Py); }
+int x_rpt_default(int L) {
+    switch (L) {
+        case 1: return x_RPT(1, 0); case 2: return x_RPT(2, 0); case 4: return x_RPT(4, 0);
+        case 8: return x_RPT(8, 0); case 16: return x_RPT(16, 0); case 32: return x_RPT(32, 0);
+        case 64: return x_RPT(64, 0); case 128: return x_RPT(128, 0); case 256: return x_RPT(256, 0);
+        case 512: return x_RPT(512, 0); case 1024: return x_RPT(1024, 0); default: return x_RPT(2048, 0);
+    }
+}
 bool ypass_split_ok(int nz, int Py) { return ysplit_ok(nz, Py); }
+
+// x passes with R = x_rows_conc(L) * RPT rows per block; RPT (rows per thread)
+// is the plan's tuned choice for each direction, 1, 2 or 4.
+template <int L, int RPT>
+static hipError_t launch_x_LR(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int mask,
+                              const float2* tw, hipStream_t s) {
+    constexpr int R = x_rows_conc(L) * RPT;
+    const int gy = c.many ? c.n : 1;
+    const dim3 grid(((a.ny + R - 1) / R) * p.S, gy);
+    const int ntiles = (a.ny + R - 1) / R;
+    if (stage == 0) {
+        if (c.many)
+            hipLaunchKernelGGL((k_xfwd<L, RPT, true>), grid, dim3(256), x_lds(L, RPT), s, c.one, c.many, p.S, ntiles, tw);
+        else
+            hipLaunchKernelGGL((k_xfwd<L, RPT, false>), grid, dim3(256), x_lds(L, RPT), s, c.one, c.many, p.S, ntiles, tw);
+    } else {
+        if (c.many)
+            hipLaunchKernelGGL((k_xinv<L, RPT, true>), grid, dim3(256), x_lds(L, RPT), s, c.one, c.many, p.S, ntiles,
+                               mask, tw);
+        else
+            hipLaunchKernelGGL((k_xinv<L, RPT, false>), grid, dim3(256), x_lds(L, RPT), s, c.one, c.many, p.S, ntiles,
+                               mask, tw);
+    }
+    return hipGetLastError();
+}
 
 template <int L>
 static hipError_t launch_x_L(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int mask,
                              const float2* tw, hipStream_t s) {
-    constexpr int RF = x_RPT(L, 0), RI = x_RPT(L, 2);
-    const int gy = c.many ? c.n : 1;
-    if (stage == 0) {
-        constexpr int R = x_rows_conc(L) * RF;
-        const dim3 grid(((a.ny + R - 1) / R) * p.S, gy);
-        const int ntiles = (a.ny + R - 1) / R;
-        if (c.many)
-            hipLaunchKernelGGL((k_xfwd<L, RF, true>), grid, dim3(256), x_lds(L, RF), s, c.one, c.many, p.S, ntiles, tw);
-        else
-            hipLaunchKernelGGL((k_xfwd<L, RF, false>), grid, dim3(256), x_lds(L, RF), s, c.one, c.many, p.S, ntiles, tw);
-    } else {
-        constexpr int R = x_rows_conc(L) * RI;
-        const dim3 grid(((a.ny + R - 1) / R) * p.S, gy);
-        const int ntiles = (a.ny + R - 1) / R;
-        if (c.many)
-            hipLaunchKernelGGL((k_xinv<L, RI, true>), grid, dim3(256), x_lds(L, RI), s, c.one, c.many, p.S, ntiles,
-                               mask, tw);
-        else
-            hipLaunchKernelGGL((k_xinv<L, RI, false>), grid, dim3(256), x_lds(L, RI), s, c.one, c.many, p.S, ntiles,
-                               mask, tw);
-    }
-    return hipGetLastError();
+    const int rpt = stage == 0 ? p.rpt_f : p.rpt_i;
+    if (rpt == 1) return launch_x_LR<L, 1>(stage, a, p, c, mask, tw, s);
+    if (rpt == 4) return launch_x_LR<L, 4>(stage, a, p, c, mask, tw, s);
+    return launch_x_LR<L, 2>(stage, a, p, c, mask, tw, s);
 }
 
 static hipError_t launch_x(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int mask,

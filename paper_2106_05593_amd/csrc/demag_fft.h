@@ -138,13 +138,13 @@ __device__ __forceinline__ int tw_src(int idx) {
 // Fill the per-pass tables with NT threads; all loads are independent so
 // they are in flight together.
 template <int N, int E, int NT>
-__device__ __forceinline__ void build_twiddles(float2* tab, const float2* __restrict__ tw) {
+__device__ __forceinline__ void build_twiddles(float2* tab, const float2* __restrict__ tw, int tid) {
     constexpr int LEN = tw_len(N, E);
     if constexpr (LEN > 0) {
 #pragma unroll
         for (int i = 0; i < (LEN + NT - 1) / NT; ++i) {
             // clamped: surplus threads rewrite the last entry with its own value
-            const int idx = min((int)threadIdx.x + NT * i, LEN - 1);
+            const int idx = min(tid + NT * i, LEN - 1);
             tab[idx] = tw[tw_src<N, E, 1, 0>(idx)];
         }
     }
@@ -258,20 +258,19 @@ constexpr int y_NSG(int nz, int Py) { return (Py <= 2048 && nz % 2 == 0) ? 6 : 3
 // ---------------------------------------------------------------------
 // x forward: a block holds R consecutive rows of one signal s.
 // ---------------------------------------------------------------------
-template <int L, int RPT, bool BAT>
-__global__ __launch_bounds__(256) void k_xfwd(ChainDesc d0, const ChainDesc* __restrict__ dl, int S, int ntiles,
-                                              const float2* __restrict__ tw) {
-    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+// Body of one x-forward block: logical block lb (tile of R rows of one
+// signal), thread tid < 256, LDS at lds.
+template <int L, int RPT>
+__device__ __forceinline__ void xfwd_body(const ChainDesc& cd, int S, int ntiles, const float2* __restrict__ tw,
+                                          int lb, int tid, float2* lds) {
     const SweepArgs a = cd.a;
     const float* __restrict__ m = cd.m;
     float2* __restrict__ X = cd.X;
     constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), R = RC * RPT;
     constexpr int LS = lds_len(L);
-    extern __shared__ float2 lds[];
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int s = lb / ntiles, y0 = (lb - s * ntiles) * R;
     const int comp = s / a.nz, z = s - comp * a.nz;
-    const int j = threadIdx.x % T, rg = threadIdx.x / T;
+    const int j = tid % T, rg = tid / T;
     // zero padding: hw <= L/2 (L >= 2), so slots n >= L/2 are zero
     constexpr int QH = E > 1 ? E / 2 : 1;
     float2 v[RPT][E];
@@ -316,7 +315,7 @@ __global__ __launch_bounds__(256) void k_xfwd(ChainDesc d0, const ChainDesc* __r
     static_assert((R * KH) % 256 == 0, "x tile covers whole waves");
 #pragma unroll 8
     for (int i = 0; i < R * KH / 256; ++i) {
-        const int e = threadIdx.x + 256 * i;
+        const int e = tid + 256 * i;
         const int k = e / R, r = e - k * R, y = y0 + r;
         const int kb = k == 0 ? KH : L - k;              // partner bin (L/2 for k = 0)
         const float2 Zk = lds[r * LS + lpad(k)];
@@ -334,28 +333,33 @@ __global__ __launch_bounds__(256) void k_xfwd(ChainDesc d0, const ChainDesc* __r
     }
 }
 
+template <int L, int RPT, bool BAT>
+__global__ __launch_bounds__(256) void k_xfwd(ChainDesc d0, const ChainDesc* __restrict__ dl, int S, int ntiles,
+                                              const float2* __restrict__ tw) {
+    extern __shared__ float2 lds[];
+    xfwd_body<L, RPT>(chain_at<BAT>(d0, dl, blockIdx.y), S, ntiles, tw, xcd_block(blockIdx.x, gridDim.x), threadIdx.x,
+                      lds);
+}
+
 // Per-pass twiddle tables of the x transforms (length L, x_E(L) per thread),
 // written once per plan after the base table.
 template <int L>
 __global__ void k_x_twiddles(float2* __restrict__ out, const float2* __restrict__ tw) {
-    build_twiddles<L, x_E(L), 256>(out, tw);
+    build_twiddles<L, x_E(L), 256>(out, tw, threadIdx.x);
 }
 
-// x inverse: mirror of k_xfwd; writes h of colour c when (mask >> c) & 1.
-template <int L, int RPT, bool BAT>
-__global__ __launch_bounds__(256) void k_xinv(ChainDesc d0, const ChainDesc* __restrict__ dl, int S, int ntiles,
-                                              int mask, const float2* __restrict__ tw) {
-    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+// x inverse: mirror of the forward; writes h of colour c when (mask >> c) & 1.
+template <int L, int RPT>
+__device__ __forceinline__ void xinv_body(const ChainDesc& cd, int S, int ntiles, int mask,
+                                          const float2* __restrict__ tw, int lb, int tid, float2* lds) {
     const SweepArgs a = cd.a;
     const float2* __restrict__ X = cd.X;
     float* __restrict__ h = cd.h;
     constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), R = RC * RPT;
     constexpr int LS = lds_len(L);
-    extern __shared__ float2 lds[];
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int s = lb / ntiles, y0 = (lb - s * ntiles) * R;
     const int comp = s / a.nz, z = s - comp * a.nz;
-    const int j = threadIdx.x % T, rg = threadIdx.x / T;
+    const int j = tid % T, rg = tid / T;
     constexpr int WSTEP = TW_N / (2 * L);
     // Z[k] = A + i B, A = X[k] + conj X[L-k], B = (X[k] - conj X[L-k]) W^-k; the
     // partner bin L-k gives Z[L-k] = conj A + i conj B, so one thread forms both
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(256) void k_xinv(ChainDesc d0, const ChainDesc* __r
     static_assert((R * KH) % 256 == 0, "x tile covers whole waves");
 #pragma unroll 8
     for (int i = 0; i < R * KH / 256; ++i) {
-        const int e = threadIdx.x + 256 * i;
+        const int e = tid + 256 * i;
         const int k = e / R, r = e - k * R, y = y0 + r;
         const int yc = y < a.ny ? y : a.ny - 1;
         const int kb = k == 0 ? KH : L - k;              // partner bin (L/2 for k = 0)
@@ -411,6 +415,14 @@ __global__ __launch_bounds__(256) void k_xinv(ChainDesc d0, const ChainDesc* __r
     }
 }
 
+template <int L, int RPT, bool BAT>
+__global__ __launch_bounds__(256) void k_xinv(ChainDesc d0, const ChainDesc* __restrict__ dl, int S, int ntiles,
+                                              int mask, const float2* __restrict__ tw) {
+    extern __shared__ float2 lds[];
+    xinv_body<L, RPT>(chain_at<BAT>(d0, dl, blockIdx.y), S, ntiles, mask, tw, xcd_block(blockIdx.x, gridDim.x),
+                      threadIdx.x, lds);
+}
+
 // Forward or inverse FFT of all S signals in groups of NSG through LDS.
 template <int PY, int E, bool INV, int NSG, int G, int S>
 __device__ __forceinline__ void y_groups(float2 (&v)[S][E], int j, const float2* __restrict__ twl, float2* lds, int ls) {
@@ -447,16 +459,21 @@ __device__ __forceinline__ void y_inv_store(float2 (&v)[S][E], int j, const floa
 // in slot PY-k for 0 < k < PY/2 (slots 0 and PY/2 already hold the real pair
 // (Y0, YL)); the merge maps the mixed (H0, HL) back to W = H0 + i HL over the
 // full range.  Works on the signals in groups of NSG through LDS.
+// (act = false: only the barriers, for thread groups that run other kx
+// values in lockstep with the kx = 0 group)
 template <int PY, int E, bool SPLIT, int NSG, int G, int S>
-__device__ __forceinline__ void y_pair(float2 (&v)[S][E], int j, float2* lds, int ls) {
+__device__ __forceinline__ void y_pair(float2 (&v)[S][E], int j, float2* lds, int ls, bool act = true) {
     if constexpr (G < S) {
         constexpr int T = PY / E;
         __syncthreads();
+        if (act) {
 #pragma unroll
-        for (int s = 0; s < NSG; ++s)
+            for (int s = 0; s < NSG; ++s)
 #pragma unroll
-            for (int q = 0; q < E; ++q) lds[s * ls + lpad(j + T * q)] = v[G + s][q];
+                for (int q = 0; q < E; ++q) lds[s * ls + lpad(j + T * q)] = v[G + s][q];
+        }
         __syncthreads();
+        if (act) {
 #pragma unroll
         for (int s = 0; s < NSG; ++s)
 #pragma unroll
@@ -471,7 +488,8 @@ __device__ __forceinline__ void y_pair(float2 (&v)[S][E], int j, float2* lds, in
                     v[G + s][q] = ky < kp ? make_float2(z.x - p.y, z.y + p.x) : make_float2(p.x + z.y, z.x - p.y);
                 }
             }
-        y_pair<PY, E, SPLIT, NSG, G + NSG, S>(v, j, lds, ls);
+        }
+        y_pair<PY, E, SPLIT, NSG, G + NSG, S>(v, j, lds, ls, act);
     }
 }
 
@@ -508,21 +526,19 @@ __device__ __forceinline__ void mix_layers(const float (&Kp)[6 * NZ], float sy, 
     }
 }
 
-// y pass: one block per kx < L (block 0 also carries kx = L), T = PY/E
-// threads; thread j owns bins j + T*q.
-template <int NZ, int PY, bool BAT>
-__global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const ChainDesc* __restrict__ dl,
-                                                            const float* __restrict__ K,
-                                                            const float2* __restrict__ tw) {
-    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+// y pass: one group of T = PY/E threads per kx < L (the kx = 0 group also
+// carries kx = L); thread j owns bins j + T*q.  nkx = L.  UNI: several groups
+// share a block (each with its own LDS), so every group runs the kx = 0
+// group's barriers too.
+constexpr int y1_lds(int nz, int Py) { return y_NSG(nz, Py) * lds_len(Py) + tw_len(Py, y_E(nz, Py)); }
+template <int NZ, int PY, bool UNI>
+__device__ __forceinline__ void ypass_body(const ChainDesc& cd, const float* __restrict__ K,
+                                           const float2* __restrict__ tw, int kx, int j, int nkx, float2* lds) {
     const SweepArgs a = cd.a;
     float2* __restrict__ X = cd.X;
     constexpr int S = 3 * NZ, E = y_E(NZ, PY), T = PY / E, NSG = y_NSG(NZ, PY);
     constexpr int LS = lds_len(PY);
-    extern __shared__ float2 lds[];
     float2* twl = lds + NSG * LS;      // per-pass twiddle tables
-    const int kx = blockIdx.x;
-    const int j = threadIdx.x;
     const int ny = a.ny;
     // zero padding: ny <= PY/2, so the upper half of each thread's strided
     // registers (y >= PY/2) is zero on input and not needed on output
@@ -537,10 +553,13 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const 
             v[s][q] = (q < QH && y < ny) ? src[y] : make_float2(0.f, 0.f);
         }
     }
-    build_twiddles<PY, E, T>(twl, tw);
+    build_twiddles<PY, E, T>(twl, tw, j);
     __syncthreads();
     y_groups<PY, E, false, NSG, 0, S>(v, j, twl, lds, LS);
     constexpr int HP = PY / 2;
+    // (the pair split and merge of the kx = 0 group sit outside the branches,
+    // so their barriers are reached by uniform control flow)
+    if (UNI || kx == 0) y_pair<PY, E, true, NSG, 0, S>(v, j, lds, LS, kx == 0);
     if (kx != 0) {
         // the tensor values of bin q+1 are loaded while bin q is mixed
         auto bin = [&](int q) {
@@ -568,9 +587,8 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const 
     } else {
         // kx = 0 in slots k <= PY/2 and kx = L in slots PY-k (both at +k);
         // the self-paired slots 0 and PY/2 mix the real pair separately
-        y_pair<PY, E, true, NSG, 0, S>(v, j, lds, LS);
         const float* K0 = K;
-        const float* KL = K + (long long)gridDim.x * (HP + 1) * 6 * NZ;
+        const float* KL = K + (long long)nkx * (HP + 1) * 6 * NZ;
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             const int ky = j + T * q;
@@ -612,8 +630,8 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const 
                 for (int s = 0; s < S; ++s) v[s][q] = H[s];
             }
         }
-        y_pair<PY, E, false, NSG, 0, S>(v, j, lds, LS);
     }
+    if (UNI || kx == 0) y_pair<PY, E, false, NSG, 0, S>(v, j, lds, LS, kx == 0);
     y_groups<PY, E, true, NSG, 0, S>(v, j, twl, lds, LS);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -624,6 +642,14 @@ __global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const 
             if (y < ny) dst[y] = v[s][q];
         }
     }
+}
+
+template <int NZ, int PY, bool BAT>
+__global__ __launch_bounds__(PY / y_E(NZ, PY)) void k_ypass(ChainDesc d0, const ChainDesc* __restrict__ dl,
+                                                            const float* __restrict__ K,
+                                                            const float2* __restrict__ tw) {
+    extern __shared__ float2 lds[];
+    ypass_body<NZ, PY, false>(chain_at<BAT>(d0, dl, blockIdx.y), K, tw, blockIdx.x, threadIdx.x, gridDim.x, lds);
 }
 
 // ---------------------------------------------------------------------
@@ -770,10 +796,10 @@ __device__ __forceinline__ float2 mf_tw_entry(int i, const float2* __restrict__ 
 // (FP16 form: the tables of the second radix-16 pass of each direction are
 // scaled by 1/16, which keeps that pass's inputs within the bound of the first)
 template <int N, int E, int NT, int PREC>
-__device__ __forceinline__ void mf_build_twiddles(float2* tab, const float2* __restrict__ tw) {
+__device__ __forceinline__ void mf_build_twiddles(float2* tab, const float2* __restrict__ tw, int tid) {
     constexpr int LEN = mf_tw_len(N, E);
     constexpr float S2 = PREC == 2 ? 0.0625f : 1.0f;
-    for (int i = threadIdx.x; i < LEN; i += NT) {
+    for (int i = tid; i < LEN; i += NT) {
         float2 v;
         if (i < mf_off_f2(N, E)) v = mf_tw_entry<E, 16, true>(i, tw);
         else if (i < mf_off_fl(N, E)) {
@@ -1005,21 +1031,22 @@ __device__ __forceinline__ void y_swap(float2 (&v)[SH][E], int g, int j, float2*
     }
 }
 
-// PREC 0: FP32 transforms on the vector units; 1, 2: split BF16 / FP16 radix-16
-// stages on the matrix cores (kmax: largest magnitude in K, for the FP16 scales).
-template <int NZ, int PY, bool BAT, int PREC>
-__global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, const ChainDesc* __restrict__ dl,
-                                                   const float* __restrict__ K,
-                                                   const float2* __restrict__ tw, float kmax) {
-    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+// Body: kx, thread tid < 2T, nkx = L, LDS at lds; UNI as for the one-set pass.
+template <int NZ, int PY> constexpr int y2_lds_bytes(int prec) {
+    return prec == 0 ? (int)sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + tw_len(PY, y2_E(NZ)))
+                     : (int)sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + mf_tw_len(PY, y2_E(NZ))) +
+                           (int)sizeof(float) * 16;
+}
+template <int NZ, int PY, int PREC, bool UNI>
+__device__ __forceinline__ void ypass2_body(const ChainDesc& cd, const float* __restrict__ K,
+                                            const float2* __restrict__ tw, float kmax, int kx, int tid, int nkx,
+                                            float2* lds) {
     const SweepArgs a = cd.a;
     float2* __restrict__ X = cd.X;
     constexpr int S = 3 * NZ, SH = S / 2, E = y2_E(NZ), HB = E / 2, T = PY / E, NSG = y2_NSG(NZ);
     constexpr int LS = lds_len(PY), HP = PY / 2, QH = E / 2;
-    extern __shared__ float2 lds[];
     float2* twl = lds + 2 * NSG * LS;
-    const int kx = blockIdx.x;
-    const int g = threadIdx.x / T, j = threadIdx.x - g * T;
+    const int g = tid / T, j = tid - g * T;
     const int ny = a.ny;
     float2 v[SH][E];
 #pragma unroll
@@ -1034,11 +1061,11 @@ __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, cons
     float2* mine = lds + g * NSG * LS;
     [[maybe_unused]] MfScales msc{1.f, 1.f, 1.f};
     if constexpr (PREC == 0) {
-        build_twiddles<PY, E, 2 * T>(twl, tw);
+        build_twiddles<PY, E, 2 * T>(twl, tw, tid);
         __syncthreads();
         y_groups<PY, E, false, NSG, 0, SH>(v, j, twl, mine, LS);
     } else {
-        mf_build_twiddles<PY, E, 2 * T, PREC>(twl, tw);
+        mf_build_twiddles<PY, E, 2 * T, PREC>(twl, tw, tid);
         if constexpr (PREC == 2) {
             // the block's largest input magnitude bounds every pass's inputs:
             // forward pass 1 (after the radix-E pass over E/2 nonzero points)
@@ -1053,7 +1080,7 @@ __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, cons
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
             float* red = (float*)(twl + mf_tw_len(PY, E));
-            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+            if ((tid & 63) == 0) red[tid >> 6] = mx;
             __syncthreads();
             mx = 0.f;
 #pragma unroll
@@ -1067,10 +1094,10 @@ __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, cons
         } else {
             __syncthreads();
         }
-        const MfDft<PREC> A = mf_dft16<PREC, false>(threadIdx.x & 63, tw);
+        const MfDft<PREC> A = mf_dft16<PREC, false>(tid & 63, tw);
         y_fwd_mf_groups<PY, E, PREC, NSG, 0, SH>(v, j, twl, mine, LS, A, msc);
     }
-    if (kx == 0) y_pair<PY, E, true, NSG, 0, SH>(v, j, mine, LS);
+    if (UNI || kx == 0) y_pair<PY, E, true, NSG, 0, SH>(v, j, mine, LS, kx == 0);
     y_swap<E, T, NSG, SH, 0>(v, g, j, lds);
     // signal s' of bin i: s' < SH ? v[s'][i] : v[s' - SH][i + HB]
     if (kx != 0) {
@@ -1113,7 +1140,7 @@ __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, cons
         // kx = 0 in slots k <= PY/2 and kx = L in slots PY-k (both at +k);
         // the self-paired slots 0 and PY/2 mix the real pair on the diagonal
         const float* K0 = K;
-        const float* KL = K + (long long)gridDim.x * (HP + 1) * 6 * NZ;
+        const float* KL = K + (long long)nkx * (HP + 1) * 6 * NZ;
 #pragma unroll
         for (int i = 0; i < HB; ++i) {
             const int ky = j + T * (i + HB * g);
@@ -1157,16 +1184,27 @@ __global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, cons
         }
     }
     y_swap<E, T, NSG, SH, 0>(v, g, j, lds);
-    if (kx == 0) y_pair<PY, E, false, NSG, 0, SH>(v, j, mine, LS);
+    if (UNI || kx == 0) y_pair<PY, E, false, NSG, 0, SH>(v, j, mine, LS, kx == 0);
     // inverse transforms group by group, each group's outputs stored as soon
     // as they are final (the stores overlap the next group's transforms)
     if constexpr (PREC == 0) {
         y_inv_store<PY, E, NSG, 0, SH, QH>(v, j, twl, mine, LS, X + ((long long)kx * S + g * SH) * ny, ny);
     } else {
-        const MfDft<PREC> Ai = mf_dft16<PREC, true>(threadIdx.x & 63, tw);
+        const MfDft<PREC> Ai = mf_dft16<PREC, true>(tid & 63, tw);
         y_inv_mf_groups<PY, E, PREC, NSG, 0, SH>(v, j, twl, mine, LS, Ai, msc, X + ((long long)kx * S + g * SH) * ny,
                                                  ny, msc.out);
     }
+}
+
+// PREC 0: FP32 transforms on the vector units; 1, 2: split BF16 / FP16 radix-16
+// stages on the matrix cores (kmax: largest magnitude in K, for the FP16 scales).
+template <int NZ, int PY, bool BAT, int PREC>
+__global__ __launch_bounds__(2 * PY / y2_E(NZ)) void k_ypass2(ChainDesc d0, const ChainDesc* __restrict__ dl,
+                                                   const float* __restrict__ K,
+                                                   const float2* __restrict__ tw, float kmax) {
+    extern __shared__ float2 lds[];
+    ypass2_body<NZ, PY, PREC, false>(chain_at<BAT>(d0, dl, blockIdx.y), K, tw, kmax, blockIdx.x, threadIdx.x,
+                                     gridDim.x, lds);
 }
 
 // Shapes whose y pass can run split-precision stages: the two-set kernel
@@ -1179,9 +1217,7 @@ constexpr bool ysplit_ok(int nz, int Py) {
 template <int NZ, int PY, int PREC>
 hipError_t launch_ypass2(const Chains& c, const DemagPlan& p, const float2* tw, hipStream_t s) {
     constexpr int E2 = y2_E(NZ);
-    constexpr size_t sh = PREC == 0 ? sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + tw_len(PY, E2))
-                                    : sizeof(float2) * (2 * y2_NSG(NZ) * lds_len(PY) + mf_tw_len(PY, E2)) +
-                                          sizeof(float) * 16;
+    constexpr size_t sh = y2_lds_bytes<NZ, PY>(PREC);
     if (c.many)
         hipLaunchKernelGGL((k_ypass2<NZ, PY, true, PREC>), dim3(p.L, c.n), dim3(2 * PY / E2), sh, s, c.one, c.many,
                            (const float*)p.K, tw, p.kmax);
@@ -1207,7 +1243,7 @@ hipError_t launch_ypass_py(const Chains& c, const DemagPlan& p, const float2* tw
         return launch_ypass2<NZ, PY, 0>(c, p, tw, s);
     } else if constexpr (3 * NZ * E <= 96) {
         if (p.prec != 0) return hipErrorInvalidValue;   // rejected at context creation
-        constexpr size_t sh = sizeof(float2) * (y_NSG(NZ, PY) * lds_len(PY) + tw_len(PY, E));
+        constexpr size_t sh = sizeof(float2) * y1_lds(NZ, PY);
         if (c.many)
             hipLaunchKernelGGL((k_ypass<NZ, PY, true>), dim3(p.L, c.n), dim3(PY / E), sh, s, c.one, c.many,
                                (const float*)p.K, tw);

@@ -83,10 +83,10 @@ void newell_tensor(double X, double Y, double Z, double hx, double hy, double hz
 // Kernel launchers (kernels.hip).
 struct DemagPlan {
     int Px, Py, L, S;
-    int rpt;          // rows per thread in the x kernels
     int logL, logPy;
     float2* X;        // [(L+1)][S][ny] complex work buffer
     float* K;         // tensor spectrum
+    int rpt_f = 2, rpt_i = 2;   // x-pass rows per thread (1, 2 or 4), forward and inverse: the tuned tile shape
     int prec;         // y-pass DFT stages: 0 FP32 (vector units), 1 split BF16, 2 split FP16 (matrix cores)
     float kmax;       // largest magnitude in K (bounds for the FP16 scales)
 };
@@ -122,6 +122,7 @@ __device__ __forceinline__ const ChainDesc& chain_at(const ChainDesc& one, const
 }
 
 int ypass_E(int nz, int Py);                    // elements per thread of the y pass
+int x_rpt_default(int L);                       // x-pass rows per thread without tuning
 bool ypass_split_ok(int nz, int Py);            // split-precision y-pass stages available for this shape
 hipError_t launch_init(const SweepArgs& a, const ClassCoef* ctab, const uint32_t* cid, float* m, int kind,
                        float dx, float dy, float dz, hipStream_t s);
@@ -143,6 +144,36 @@ hipError_t launch_end_sweep(const Chains& c, int shift, long long N, double* ser
 hipError_t launch_energy(const SweepArgs& a, bool classes, bool cubic, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out);
 hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s);
+// Persistent batched sweeps (persist.hip): one kernel advances every chain of
+// a batch; chains of uniform material without DMI, demag off or FP32 with nz
+// 1 or 2, x half-length 32..1024 and padded y 64..1024 (persist_shape_ok).
+struct PersistChain {
+    ChainDesc cd;
+    const float* K;        // tensor spectrum (demag)
+    const float2* tw;      // twiddle tables (demag)
+    int L, Py;             // x half-length and padded y of the demag plan
+    bool demag;
+    int refresh_per_sweep;
+    int shift;             // fixed-point scale of the statistics
+};
+struct PersistPlan {
+    int nch = 0, W = 0, grid = 0;
+    size_t lds = 0;
+    bool exact = false;    // length move of every chain (one kernel per kind)
+    void* mem = nullptr;   // device block holding the tables and counters
+    void* pc = nullptr;
+    int *off = nullptr, *pre = nullptr, *wc = nullptr;
+    unsigned long long* ctr = nullptr;
+    int* err = nullptr;
+    std::vector<int> host_off, host_pre, host_wc;
+};
+bool persist_shape_ok(int nx, int ny, int nz, bool demag);
+hipError_t persist_build(const PersistChain* in, int n, PersistPlan* out);   // out->exact set by the caller
+// n sweeps of every chain: a counter reset and the persistent kernel on s;
+// a wait longer than limit_s seconds sets the plan's error flag.
+hipError_t persist_launch(const PersistPlan& p, int nsweeps, double limit_s, hipStream_t s);
+void persist_free(PersistPlan* p);
+
 // Energy partials: k_energy never runs more than kEnergyMaxBlocks blocks
 // (it strides over the grid).
 constexpr int kEnergyMaxBlocks = 2048;

@@ -20,6 +20,8 @@ MMC_DEMAG_OFF, MMC_DEMAG_FP32, MMC_DEMAG_SPLIT_BF16, MMC_DEMAG_SPLIT_FP16 = 0, 1
 _DEMAG_MODES = {False: MMC_DEMAG_OFF, True: MMC_DEMAG_FP32, "off": MMC_DEMAG_OFF, "fp32": MMC_DEMAG_FP32,
                 "split_bf16": MMC_DEMAG_SPLIT_BF16, "split_fp16": MMC_DEMAG_SPLIT_FP16}
 MMC_ANIS_UNIAXIAL, MMC_ANIS_CUBIC = 0, 1
+MMC_SCHED_AUTO, MMC_SCHED_GROUPS, MMC_SCHED_PERSISTENT = 0, 1, 2
+_SCHEDS = {"auto": MMC_SCHED_AUTO, "groups": MMC_SCHED_GROUPS, "persistent": MMC_SCHED_PERSISTENT}
 MUB = 9.2740100783e-24
 
 
@@ -80,6 +82,7 @@ _SIGS = {
     "mmc_demag_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_subsweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mmc_get_stats": (C.c_int, [C.c_void_p, C.POINTER(mmc_stats)]),
+    "mmc_get_tuning": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mmc_take_averages": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "mmc_get_state": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
     "mmc_set_state": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint64]),
@@ -87,6 +90,8 @@ _SIGS = {
     "mmc_batch_sweep": (C.c_int, [C.c_void_p, C.c_int32]),
     "mmc_batch_sync": (C.c_int, [C.c_void_p]),
     "mmc_batch_destroy": (None, [C.c_void_p]),
+    "mmc_batch_set_schedule": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mmc_batch_get_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "mmc_sync": (C.c_int, [C.c_void_p]),
     "mmc_status_str": (C.c_char_p, [C.c_int]),
     "mmc_last_error": (C.c_char_p, []),
@@ -298,6 +303,14 @@ class Chain:
         return {"sweeps": s.sweeps, "accepts_window": s.accepts_window, "cone_deg": s.cone_deg, "sigma": s.sigma,
                 "me": s.me, "m_mean": list(s.m_mean), "m2_mean": s.m2_mean, "accepts_last": s.accepts_last}
 
+    def tuning(self):
+        """(rows per thread of the x passes (forward, inverse), us per launch of
+        the candidates 1, 2, 4 for each direction)."""
+        rpt = np.zeros(2, dtype=np.int32)
+        us = np.zeros(6)
+        _check(lib().mmc_get_tuning(self._h, rpt.ctypes.data, us.ctypes.data))
+        return tuple(int(v) for v in rpt), us
+
     def get_state(self):
         sw, cd, win = C.c_uint64(), C.c_int32(), C.c_uint64()
         _check(lib().mmc_get_state(self._h, C.byref(sw), C.byref(cd), C.byref(win)))
@@ -311,14 +324,29 @@ class Chain:
 
 
 class Batch:
-    """Independent chains advanced together by one HIP graph launch per call."""
+    """Independent chains advanced together by one HIP graph launch per call.
 
-    def __init__(self, chains):
+    schedule: 'auto' (timed choice), 'groups' (shape groups sharing launches)
+    or 'persistent' (one persistent kernel for every chain)."""
+
+    def __init__(self, chains, schedule="auto"):
         self.chains = list(chains)
         arr = (C.c_void_p * len(self.chains))(*[c.handle.value for c in self.chains])
         h = C.c_void_p()
         _check(lib().mmc_batch_create(arr, len(self.chains), C.byref(h)))
         self._h = h
+        if schedule != "auto":
+            self.set_schedule(schedule)
+
+    def set_schedule(self, schedule):
+        _check(lib().mmc_batch_set_schedule(self._h, _SCHEDS[schedule]))
+
+    def schedule(self):
+        """(form in use: 'groups' or 'persistent', trial ms of (groups, persistent))."""
+        used = C.c_int32()
+        ms = np.zeros(2)
+        _check(lib().mmc_batch_get_schedule(self._h, C.byref(used), ms.ctypes.data))
+        return {v: k for k, v in _SCHEDS.items()}[used.value], ms
 
     def sweep(self, n):
         _check(lib().mmc_batch_sweep(self._h, int(n)))
