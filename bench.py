@@ -75,8 +75,46 @@ def counted_traffic(kernel):
     return rec["bytes_per_launch"][kernel]["total"]
 
 
+def host_cpu():
+    """CPU model, logical CPUs and physical cores of this host (from /proc/cpuinfo)."""
+    model, cores, logical = None, set(), 0
+    phys = core = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "processor":
+                logical += 1
+            elif k == "model name" and model is None:
+                model = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None and core is not None:
+                cores.add((phys, core))
+                phys = core = None
+        if phys is not None and core is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": logical or os.cpu_count(), "physical_cores": len(cores) or None}
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of the oracle library (it links libgomp)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
 def cpu_baseline(seconds_target=15.0):
-    """The FP64 oracle (as it stands) on a 256x256x4 section of the same workload."""
+    """The FP64 oracle (as it stands) on a 256x256x4 section of the same
+    workload (same cell, material, T, field, demag), timed with all host
+    threads and with one thread."""
     from oracle import oracle as O
     wl = workloads.WORKLOADS["loop_1024x1024x4"]
     mat = workloads.BASE_MATERIAL
@@ -85,22 +123,36 @@ def cpu_baseline(seconds_target=15.0):
                  B=wl["B"], demag=True, mf=mat["mf"])
     m = S.init_state("uniform")
     _ = S.plan                                       # tensor setup, not timed (as on the GPU side)
-    S.run(m, 1, cone_deg=30, adapt_every=100)        # warm-up sweep
-    n, t = 0, 0.0
-    while t < seconds_target and n < 200:
-        t0 = time.perf_counter()
-        S.run(m, 2, sweep0=1 + n, cone_deg=30, adapt_every=100)
-        t += time.perf_counter() - t0
-        n += 2
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cells = int(np.prod(grid))
-    return {"value": cells * n / t, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": "%d sweeps of a 256x256x4 section (same cell, material, T, field, demag on), %.1f s" % (n, t)}
+    cpu = host_cpu()
+    threads_all = int(os.environ.get("OMP_NUM_THREADS", cpu["logical_cpus"] or 1))
+
+    def rate(threads, budget, sweep0):
+        _omp_threads(threads)
+        S.run(m, 1, sweep0=sweep0, cone_deg=30, adapt_every=100)        # warm-up sweep
+        n, t = 0, 0.0
+        while t < budget and n < 200:
+            t0 = time.perf_counter()
+            S.run(m, 2, sweep0=sweep0 + 1 + n, cone_deg=30, adapt_every=100)
+            t += time.perf_counter() - t0
+            n += 2
+        return cells * n / t, n, t
+    v_all, n_all, t_all = rate(threads_all, seconds_target, 0)
+    v_one, n_one, t_one = rate(1, max(2.0, seconds_target / 3), 1000)
+    _omp_threads(threads_all)
+    return {"value": v_all, "unit": "cell-updates/s", "cores": threads_all, "kind": "oracle",
+            "sample": "%d sweeps of a 256x256x4 section (same cell, material, T, field, demag on) in %.1f s with %d "
+                      "threads; %d sweeps in %.1f s with 1 thread" % (n_all, t_all, threads_all, n_one, t_one),
+            "value_1thread": v_one, "cpu_model": cpu["model"], "logical_cpus": cpu["logical_cpus"],
+            "physical_cores": cpu["physical_cores"]}
 
 
-def batched_leg(n_chains=64, sweeps=100, seed=0):
-    """Independent chains of uneven size, T and field: one HIP-graph launch per
-    call (batched) against the same chains run one after another (plain)."""
+def batched_leg(n_chains=64, sweeps=1000, seed=0):
+    """Independent chains of uneven size, T and field (64 chains drawn from
+    64^2x1, 128^2x1, 256^2x2, 512^2x2 cells of 5 nm, T in [0.2, 1.2] Tc, Hz in
+    [-0.5, 0.5] T, demag on), `sweeps` sweeps each: one batch call (one HIP
+    graph launch) against the same chains run one at a time (each chain's
+    sweeps, then a synchronisation, then the next chain)."""
     import torch
     from paper_2106_05593_amd import Batch, Chain
     mat = workloads.BASE_MATERIAL
@@ -114,30 +166,138 @@ def batched_leg(n_chains=64, sweeps=100, seed=0):
     cells = sum(int(np.prod(p["grid"])) for p in params)
     for c in chains:                                   # warm-up, one at a time
         c.sweep(2)
-    for c in chains:
         c.sync()
     t0 = time.perf_counter()
     for c in chains:
         c.sweep(sweeps)
-    for c in chains:
         c.sync()
     t_plain = time.perf_counter() - t0
     b = Batch(chains)
-    b.sweep(sweeps)                                    # captures the graph (first call)
+    b.sweep(sweeps)                                    # schedule choice and graph capture (first call)
     b.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.sweep(sweeps)
     b.sync()
     t_batch = time.perf_counter() - t0
+    used, trial = b.schedule()
     b.close()
     for c in chains:
         c.close()
-    scale = 1000.0 / sweeps                            # chains of 1000 sweeps each
-    return {"chains": n_chains, "cells": cells, "timed_sweeps_per_chain": sweeps,
-            "chains_per_s_batched": n_chains / (t_batch * scale), "chains_per_s_plain": n_chains / (t_plain * scale),
+    return {"chains": n_chains, "cells": cells, "sweeps_per_chain": sweeps, "schedule": used,
+            "chains_per_s_batched": n_chains / t_batch, "chains_per_s_plain": n_chains / t_plain,
             "cell_updates_per_s_batched": cells * sweeps / t_batch, "cell_updates_per_s_plain": cells * sweeps / t_plain,
             "speedup": t_plain / t_batch}
+
+
+def granular_leg(sweeps=60, warmup=5, every=10, seed=0):
+    """Granular medium (512x512x8 cells of 3 nm; 3-D Voronoi grains of 10 nm
+    mean seed spacing; per-grain easy axis within 10 deg of z, Ku 0.7 MJ/m^3,
+    Tc ~ N(700 K, 35 K); exchange across grain boundaries x0.1; 600 K; demag
+    before each colour pass) with the y-direction DFT stages in FP32 and as
+    split BF16 / FP16 matrix products: cell-updates/s per precision, the
+    y-pass time, the relative L2 difference of the demag field of one state
+    from the FP32 field, and <m> after the timed sweeps."""
+    import torch
+    from paper_2106_05593_amd import Chain
+    wl = workloads.WORKLOADS["granular_512x512x8"]
+    mat = workloads.BASE_MATERIAL
+    grid, cell = wl["grid"], wl["cell"]
+    N = int(np.prod(grid))
+    gid, ng = workloads.voronoi_grains(grid, cell, 10e-9, seed=4)
+    ea, K1, K2, Tc = workloads.grain_properties(ng, seed=5)
+    m_probe = workloads.random_state(N, seed=6)
+    out = {"workload": "granular_512x512x8", "grains": int(ng), "sweeps": sweeps, "modes": {}}
+    h_ref = None
+    for mode in ("fp32", "split_bf16", "split_fp16"):
+        ch = Chain(grid, cell, Ms0=mat["Ms0"], A0=mat["A0"], K1=0.0, Tc=mat["Tc"], T=wl["T"], B=wl["B"],
+                   mf=mat["mf"], mu=mat["mu"], demag=mode, adapt_every=100, seed=seed, init=1)
+        ch.set_grains(gid, ea, K1, K2, Tc, 0.1)
+        state = ch.get_m()
+        ch.set_m(m_probe)
+        h = ch.demag_field().astype(np.float64)
+        if h_ref is None:
+            h_ref = h
+        ch.set_m(state)
+        ch.sweep(warmup)
+        ch.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms, cnt = ch.sweep_timed(sweeps, every=every)
+        wall = time.perf_counter() - t0
+        st = ch.stats()
+        out["modes"][mode] = {"cell_updates_per_s": N * sweeps / wall, "ms_per_sweep": 1e3 * wall / sweeps,
+                              "ypass_us": round(1e3 * ms[1] / cnt[1], 2),
+                              "field_rel_l2_vs_fp32": float(np.linalg.norm(h - h_ref) / np.linalg.norm(h_ref)),
+                              "m_mean": [round(v, 6) for v in st["m_mean"]], "m2_mean": round(st["m2_mean"], 6)}
+        ch.close()
+    return out
+
+
+def dmi_film_leg(sweeps=10000, seed=0):
+    """DMI thin film with demag (256x256x1 cells of 4x4x2 nm, D0 1.5 mJ/m^2,
+    T 0.5 Tc, zero field, random start): `sweeps` sweeps, wall time and
+    cell-updates/s."""
+    import torch
+    from paper_2106_05593_amd import Chain
+    wl = workloads.WORKLOADS["film_256x256x1"]
+    mat = workloads.BASE_MATERIAL
+    grid = wl["grid"]
+    N = int(np.prod(grid))
+    ch = Chain(grid, wl["cell"], Ms0=mat["Ms0"], A0=mat["A0"], K1=mat["K1"], D0=wl["D0"], Tc=mat["Tc"], T=wl["T"],
+               B=wl["B"], mf=mat["mf"], mu=mat["mu"], demag=True, adapt_every=100, seed=seed, init=1)
+    ch.sweep(5)
+    ch.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.sweep(sweeps)
+    ch.sync()
+    wall = time.perf_counter() - t0
+    st = ch.stats()
+    ch.close()
+    return {"workload": "film_256x256x1", "sweeps": sweeps, "wall_s": wall, "cell_updates_per_s": N * sweeps / wall,
+            "m2_mean": st["m2_mean"]}
+
+
+def loop_leg(temperatures=(630.0, 770.0), sweeps_per_point=200, seed=0):
+    """The hysteresis-loop workload as a whole: 1024x1024x4 cells of 5 nm with
+    demag, field along z from +1 T to -1 T in 0.01 T steps and back (401
+    points), 200 sweeps per point, the point's value the mean of sweeps
+    101-200 (FP64 means of every sweep), at each temperature: loop wall time
+    and cell-updates/s over the whole loop."""
+    import torch
+    from paper_2106_05593_amd import Chain
+    wl = workloads.WORKLOADS["loop_1024x1024x4"]
+    mat = workloads.BASE_MATERIAL
+    grid = wl["grid"]
+    N = int(np.prod(grid))
+    fields = np.concatenate([np.linspace(1.0, -1.0, 201), np.linspace(-0.99, 1.0, 200)])
+    out = {"workload": "loop_1024x1024x4", "points": len(fields), "sweeps_per_point": sweeps_per_point, "runs": {}}
+    for T in temperatures:
+        ch = Chain(grid, wl["cell"], Ms0=mat["Ms0"], A0=mat["A0"], K1=mat["K1"], Tc=mat["Tc"], T=T, B=(0, 0, 1.0),
+                   mf=mat["mf"], mu=mat["mu"], demag=True, adapt_every=100, seed=seed, init=0)
+        ch.sweep(2)
+        ch.sync()
+        torch.cuda.synchronize()
+        half = sweeps_per_point // 2
+        mz = []
+        t0 = time.perf_counter()
+        for i, b in enumerate(fields):
+            ch.set_field((0.0, 0.0, float(b)))
+            ch.sweep(half)
+            ch.take_averages()                   # drops the first half
+            ch.sweep(sweeps_per_point - half)
+            avg, n = ch.take_averages()
+            mz.append(avg[2])
+            if i % 50 == 0:
+                print("bench: loop T=%.0f K point %d/%d" % (T, i, len(fields)), file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        ch.close()
+        sweeps = len(fields) * sweeps_per_point
+        out["runs"]["%.0f K" % T] = {"wall_s": wall, "sweeps": sweeps, "cell_updates_per_s": N * sweeps / wall,
+                                     "mz_at_+1T": mz[0], "mz_at_-1T": mz[200], "mz_at_0T_down": mz[100],
+                                     "mz_at_0T_up": mz[300]}
+    return out
 
 
 def fe_film_leg(sweeps=100, warmup=5, every=10, seed=0):
@@ -224,6 +384,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fe-film", action="store_true")
     ap.add_argument("--no-profile-leg", action="store_true")
+    ap.add_argument("--no-granular", action="store_true")
+    ap.add_argument("--no-dmi-film", action="store_true")
+    ap.add_argument("--loop-leg", action="store_true", help="also run the whole 401-point loop at 630 K and 770 K")
     ap.add_argument("--profile-every", type=int, default=10,
                     help="bracket every kernel of one timed sweep in this many with HIP events")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -303,6 +466,15 @@ def main():
     if not args.no_profile_leg:
         print("bench: temperature-profile leg", file=sys.stderr, flush=True)
         out["temperature_profile"] = profile_leg()
+    if not args.no_granular:
+        print("bench: granular 512x512x8 leg (FP32 and split demag stages)", file=sys.stderr, flush=True)
+        out["granular"] = granular_leg()
+    if not args.no_dmi_film:
+        print("bench: DMI film leg", file=sys.stderr, flush=True)
+        out["dmi_film"] = dmi_film_leg()
+    if args.loop_leg:
+        print("bench: whole-loop leg", file=sys.stderr, flush=True)
+        out["loop"] = loop_leg()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
