@@ -23,7 +23,7 @@ import numpy as np  # noqa: E402
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KINDS = ["demag_xfwd", "demag_ypass", "demag_xinv", "colour_pass", "end_of_sweep"]
+KINDS = ["demag_xfwd", "demag_ypass", "demag_xinv", "colour_pass", "end_of_sweep", "fused_pass"]
 
 
 def pad_pow2(n, minimum=1):
@@ -50,6 +50,8 @@ def algorithmic_bytes(grid, demag, kind):
     if kind == "colour_pass":
         per = 12 + 12 + 12 + (12 if demag else 0)   # own m, other m, own write, own h
         return per * N // 2
+    if kind == "fused_pass":
+        return 2 * spec + 12 * N + 6 * N            # spectrum in and out, m read, own colour written
     return 0
 
 

@@ -222,8 +222,13 @@ mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series);
  * device time (ms) and the launch count per kernel kind over the sampled
  * sweeps:
  * 0 demag x-forward FFT, 1 demag y-pass (FFT, layer mixing, inverse FFT),
- * 2 demag x-inverse FFT, 3 colour pass, 4 end-of-sweep statistics. */
-mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[5], int32_t launches_out[5]);
+ * 2 demag x-inverse FFT, 3 colour pass, 4 end-of-sweep statistics,
+ * 5 fused colour pass (x-inverse of the field, the colour pass and the
+ * x-forward of the updated rows in one kernel: chains of uniform material
+ * with nx % 8 == 0 and the field refreshed before each colour; a sweep call
+ * then starts with one x-forward; MMC_FUSE=0 in the environment at
+ * mmc_create keeps the separate kernels for that context). */
+mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[6], int32_t launches_out[6]);
 
 /* Total free energy (J) of the current state and its split {exchange (Eq. 10
  * as the bond sum), DMI (Eq. 15), anisotropy (Eq. 11 or 12), Zeeman,
@@ -294,8 +299,16 @@ mmc_status mmc_take_averages(mmc_ctx* ctx, double avg_out[4], uint64_t* n_out);
  * us_per_launch is not NULL, the measured microseconds per launch of the
  * candidates (forward 1, 2, 4, inverse 1, 2, 4; zeros when not tuned).
  * MMC_TUNE=1, 2 or 4 forces that many rows per thread in both directions.
- * Errors: MMC_ERR_STATE without demag. */
-mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_per_launch[6]);
+ * Also decided at mmc_create: whether the colour passes run fused with the
+ * x transforms around them (see mmc_sweep_timed, kind 5) or as separate
+ * kernels: for chains that allow it, one colour of each form is timed from
+ * the state (restored afterwards, so the chain is unchanged; both forms give
+ * the same bits), the faster is kept and cached per shape; MMC_FUSE=0 or 1
+ * forces the form.  *fused (may be NULL) is 1 when the fused form runs;
+ * fuse_us (may be NULL) the timed us per colour of the separate and the
+ * fused form (zeros when not timed).  Errors: MMC_ERR_STATE without demag. */
+mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_per_launch[6], int32_t* fused,
+                          double fuse_us[2]);
 
 /* Run state for checkpoint/resume: the sweep counter, cone angle and accept
  * window; with the state m (mmc_get_m / mmc_set_m) this restores a chain

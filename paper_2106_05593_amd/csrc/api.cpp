@@ -91,6 +91,8 @@ struct mmc_ctx {
     bool demag = false;
     DemagPlan plan{};
     double xtune_us[6] = {0, 0, 0, 0, 0, 0};   // x-pass tuning: us per launch of each candidate
+    int fuse = -1;               // fused colour passes: 1 on, 0 off, -1 not decided (tuned at creation)
+    double fuse_us[2] = {0, 0};  // tuning: us per colour of the separate kernels and of the fused kernel
     float2* d_tw = nullptr;
     SweepArgs args{};
     unsigned long long host_sweep = 0;
@@ -197,13 +199,21 @@ static mmc_status init_state(mmc_ctx* ctx) {
 
 // Launch sequence of n sweeps.  With `prof`, HIP events bracket every launch
 // (kinds: 0 demag x-forward, 1 demag y-pass, 2 demag x-inverse, 3 colour pass,
-// 4 end of sweep).
+// 4 end of sweep, 5 fused x-inverse + colour pass + x-forward).
 struct LaunchProf {
     std::vector<hipEvent_t> ev;
     std::vector<int> kind;
     size_t used = 0;
     int every = 1;    // instrument sweeps 0, every, 2*every, ...
 };
+
+// The fused colour pass serves chains of uniform material, nx % 8 == 0 and
+// the field refreshed before each colour; MMC_FUSE=0 in the environment at
+// mmc_create keeps the separate kernels for that context.
+static bool fuse_eligible(const mmc_ctx* c) {
+    return c->demag && c->run.refresh_per_sweep >= 2 && !c->cubic && fused_ok(c->args, c->plan.L, c->has_classes);
+}
+static bool use_fused(const mmc_ctx* c) { return c->fuse == 1 && fuse_eligible(c); }
 
 // n sweeps of the chains ch, all of c0's shape, on stream st.
 static mmc_status enqueue_core(mmc_ctx* c0, const Chains& ch, int n, hipStream_t st, double* series,
@@ -217,6 +227,29 @@ static mmc_status enqueue_core(mmc_ctx* c0, const Chains& ch, int n, hipStream_t
         return hipEventRecord(prof->ev[prof->used++], st);
     };
     const bool exact = c0->run.lenmove == MMC_LEN_EXACT, dmi = c0->mat.D0 != 0.0;
+    if (n > 0 && use_fused(c0)) {
+        // x-spectrum of the current state, then per colour: y pass, fused pass
+        // (which leaves the updated state's x-spectrum for the next y pass)
+        sw = 0;
+        HIPCK(mark(-1));
+        HIPCK(launch_demag_stage(0, c0->args, c0->plan, ch, 3, c0->d_tw, st));
+        HIPCK(mark(0));
+        for (int s = 0; s < n; ++s) {
+            sw = s;
+            for (int c = 0; c < 2; ++c) {
+                HIPCK(mark(-1));
+                HIPCK(launch_demag_stage(1, c0->args, c0->plan, ch, 1 << c, c0->d_tw, st));
+                HIPCK(mark(1));
+                HIPCK(mark(-1));
+                HIPCK(launch_fused(c0->args, c0->plan, exact, dmi, ch, c, c0->fp_shift, c0->d_tw, st));
+                HIPCK(mark(5));
+            }
+            HIPCK(mark(-1));
+            HIPCK(launch_end_sweep(ch, c0->fp_shift, c0->N, series, rec_base, st));
+            HIPCK(mark(4));
+        }
+        return MMC_OK;
+    }
     for (int s = 0; s < n; ++s) {
         sw = s;
         for (int c = 0; c < 2; ++c) {
@@ -299,6 +332,8 @@ static mmc_status tune_x(mmc_ctx* ctx) {
         const int stage = d == 0 ? 0 : 2;
         double best = 1e30;
         for (int r = 0; r < 3 && st == MMC_OK; ++r) {
+            // candidates whose blocks need more than 96 KiB of LDS (two per CU) are skipped
+            if (rpts[r] != x_rpt_default(p.L) && x_pass_lds(p.L, rpts[r]) > 96 * 1024) continue;
             (d == 0 ? p.rpt_f : p.rpt_i) = rpts[r];
             hipError_t e = hipSuccess;
             for (int k = 0; k < kWarm + kTimed && e == hipSuccess; ++k) {
@@ -323,6 +358,86 @@ static mmc_status tune_x(mmc_ctx* ctx) {
     std::copy(t.us, t.us + 6, ctx->xtune_us);
     std::lock_guard<std::mutex> lk(g_xtune_mu);
     g_xtune[key] = t;
+    return MMC_OK;
+}
+
+// Fused or separate colour passes: one colour of each form (x-inverse, colour
+// pass, x-forward against the fused kernel) is timed from the same state,
+// which is restored afterwards (m, run state and statistics accumulators; the
+// spectrum and field buffers are recomputed before every use), and the faster
+// form is kept; the choice is cached per shape.  Both forms give the same bits.
+static std::mutex g_fuse_mu;
+static std::map<std::string, std::pair<int, std::pair<double, double>>> g_fuse;
+
+static mmc_status tune_fuse(mmc_ctx* ctx) {
+    if (!fuse_eligible(ctx)) { ctx->fuse = 0; return MMC_OK; }
+    char key[96];
+    snprintf(key, sizeof key, "%d,%d,%d,%d,%d", ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->run.lenmove, ctx->mat.D0 != 0.0);
+    {
+        std::lock_guard<std::mutex> lk(g_fuse_mu);
+        auto it = g_fuse.find(key);
+        if (it != g_fuse.end()) {
+            ctx->fuse = it->second.first;
+            ctx->fuse_us[0] = it->second.second.first;
+            ctx->fuse_us[1] = it->second.second.second;
+            return MMC_OK;
+        }
+    }
+    const size_t mb = sizeof(float) * 6 * (size_t)ctx->Nc;
+    const size_t tot = mb + sizeof(DevState) + sizeof(SweepAccum);
+    void* snap = nullptr;
+    if (hipMalloc(&snap, tot) != hipSuccess) return fail(MMC_ERR_OOM, "tuning snapshot");
+    char* p = (char*)snap;
+    auto save = [&](bool restore) -> hipError_t {
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        hipError_t e = restore ? hipMemcpyAsync(ctx->d_m, p, mb, k, ctx->stream) : hipMemcpyAsync(p, ctx->d_m, mb, k, ctx->stream);
+        if (e == hipSuccess)
+            e = restore ? hipMemcpyAsync(ctx->d_st, p + mb, sizeof(DevState), k, ctx->stream)
+                        : hipMemcpyAsync(p + mb, ctx->d_st, sizeof(DevState), k, ctx->stream);
+        if (e == hipSuccess)
+            e = restore ? hipMemcpyAsync(ctx->d_acc, p + mb + sizeof(DevState), sizeof(SweepAccum), k, ctx->stream)
+                        : hipMemcpyAsync(p + mb + sizeof(DevState), ctx->d_acc, sizeof(SweepAccum), k, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        return e;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = save(false);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const bool exact = ctx->run.lenmove == MMC_LEN_EXACT, dmi = ctx->mat.D0 != 0.0;
+    const Chains one = single(ctx);
+    double us[2] = {0, 0};
+    constexpr int kWarm = 1, kTimed = 3;
+    for (int form = 0; form < 2 && e == hipSuccess; ++form) {
+        for (int k = 0; k < kWarm + kTimed && e == hipSuccess; ++k) {
+            if (k == kWarm) e = hipEventRecord(e0, ctx->stream);
+            if (e != hipSuccess) break;
+            if (form == 0) {
+                e = launch_demag_stage(2, ctx->args, ctx->plan, one, 1, ctx->d_tw, ctx->stream);
+                if (e == hipSuccess)
+                    e = launch_pass(ctx->args, false, true, exact, dmi, false, one, 0, true, ctx->fp_shift, nullptr,
+                                    ctx->stream);
+                if (e == hipSuccess) e = launch_demag_stage(0, ctx->args, ctx->plan, one, 3, ctx->d_tw, ctx->stream);
+            } else {
+                e = launch_fused(ctx->args, ctx->plan, exact, dmi, one, 0, ctx->fp_shift, ctx->d_tw, ctx->stream);
+            }
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        us[form] = 1e3 * ms / kTimed;
+        if (e == hipSuccess) e = save(true);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(snap);
+    if (e != hipSuccess) return fail(MMC_ERR_DEVICE, "fusion tuning: %s", hipGetErrorString(e));
+    ctx->fuse = us[1] < us[0] ? 1 : 0;
+    ctx->fuse_us[0] = us[0];
+    ctx->fuse_us[1] = us[1];
+    std::lock_guard<std::mutex> lk(g_fuse_mu);
+    g_fuse[key] = {ctx->fuse, {us[0], us[1]}};
     return MMC_OK;
 }
 
@@ -405,6 +520,10 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
     do {
         ctx->g = *grid; ctx->cs = *cell; ctx->mat = *mat; ctx->run = *run;
         if (hipGetDevice(&ctx->device) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "no HIP device"); break; }
+        {
+            const char* fe = getenv("MMC_FUSE");
+            ctx->fuse = (fe && fe[0] == '0') ? 0 : ((fe && fe[0] == '1') ? 1 : -1);
+        }
         // set-up of mmc_energy_noalloc's scratch on this device (once per device)
         {
             const hipError_t e = energy_scratch_init(ctx->device);
@@ -484,6 +603,7 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
         }
         st = init_state(ctx);
         if (st == MMC_OK && ctx->demag) st = tune_x(ctx);
+        if (st == MMC_OK && ctx->fuse < 0) st = tune_fuse(ctx);
     } while (false);
     if (st != MMC_OK) {
         mmc_destroy(ctx);
@@ -654,7 +774,7 @@ mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n) {
     return enqueue_sweeps(ctx, n, nullptr, 0);
 }
 
-mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[5], int32_t launches_out[5]) {
+mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[6], int32_t launches_out[6]) {
     mmc_status s = check_live(ctx);
     if (s != MMC_OK) return s;
     if (n < 0 || every < 1 || !ms_out || !launches_out) return fail(MMC_ERR_ARG, "bad count, sampling or NULL output");
@@ -669,7 +789,7 @@ mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out
         if (hipEventCreate(&prof.ev[made]) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "event creation failed"); break; }
     if (st == MMC_OK) st = enqueue_sweeps(ctx, n, nullptr, 0, &prof);
     if (st == MMC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(MMC_ERR_DEVICE, "synchronize failed");
-    for (int k = 0; k < 5; ++k) { ms_out[k] = 0.0; launches_out[k] = 0; }
+    for (int k = 0; k < 6; ++k) { ms_out[k] = 0.0; launches_out[k] = 0; }
     if (st == MMC_OK) {
         for (size_t i = 0; i < prof.kind.size(); ++i) {
             float ms = 0.f;
@@ -781,7 +901,8 @@ mmc_status mmc_subsweep(mmc_ctx* ctx, int32_t colour, const float* h_in, uint8_t
     return MMC_OK;
 }
 
-mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_per_launch[6]) {
+mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_per_launch[6], int32_t* fused,
+                          double fuse_us[2]) {
     mmc_status s = check_live(ctx);
     if (s != MMC_OK) return s;
     if (!rows_per_thread) return fail(MMC_ERR_ARG, "NULL output");
@@ -789,6 +910,8 @@ mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_pe
     rows_per_thread[0] = ctx->plan.rpt_f;
     rows_per_thread[1] = ctx->plan.rpt_i;
     if (us_per_launch) std::copy(ctx->xtune_us, ctx->xtune_us + 6, us_per_launch);
+    if (fused) *fused = use_fused(ctx) ? 1 : 0;
+    if (fuse_us) { fuse_us[0] = ctx->fuse_us[0]; fuse_us[1] = ctx->fuse_us[1]; }
     return MMC_OK;
 }
 

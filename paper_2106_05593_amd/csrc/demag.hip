@@ -16,6 +16,11 @@ extern template hipError_t launch_ypass_nz<7>(const Chains&, const DemagPlan&, c
 extern template hipError_t launch_ypass_nz<8>(const Chains&, const DemagPlan&, const float2*, hipStream_t);
 
 int ypass_E(int nz, int Py) { return y_E(nz, Py); }
+size_t x_pass_lds(int L, int rpt) {
+    for (int l = 1; l <= 2048; l *= 2)
+        if (l == L) return (size_t)x_rows_conc(l) * rpt * lds_len(l) * sizeof(float2);
+    return 0;
+}
 int x_rpt_default(int L) {
     switch (L) {
         case 1: return x_RPT(1, 0); case 2: return x_RPT(2, 0); case 4: return x_RPT(4, 0);

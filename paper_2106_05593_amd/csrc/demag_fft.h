@@ -41,14 +41,20 @@ template <bool INV> __device__ __forceinline__ float2 twc(float2 a, float c, flo
     return INV ? make_float2(a.x * c - a.y * s, a.x * s + a.y * c) : make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
 }
 
-// LDS index with one slot of skew every 16 float2 (a 16-lane group of 8-byte
-// accesses covers all 32 banks once when its slots differ mod 16); the
-// per-signal stride is kept at 1 mod 16 so the same slot of consecutive
-// signals falls in different banks.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// LDS index with one slot of skew every 32 float2 (the 32 lanes that one
+// 8-byte access serves per cycle cover the 64 banks once when their slots
+// differ mod 32; one slot per 32 measured 3 % faster than one per 16 on the y
+// pass, whose radix-8 first-pass writes it makes conflict-free); the
+// per-signal stride is kept at 1 mod 32.  With power-of-two passes the
+// outputs of a butterfly stay at lpad(base) + r*NSUB + (r*NSUB >> kSkew).
+#ifndef MMC_LDS_SKEW
+#define MMC_LDS_SKEW 5
+#endif
+constexpr int kSkew = MMC_LDS_SKEW, kSkewP = 1 << MMC_LDS_SKEW;   // one slot of skew per kSkewP slots
+__device__ __forceinline__ int lpad(int i) { return i + (i >> kSkew); }
 constexpr int lds_len(int n) {
-    const int l = n - 1 + ((n - 1) >> 4) + 1;
-    return l + ((17 - l % 16) % 16);   // round up to 1 mod 16
+    const int l = n - 1 + ((n - 1) >> kSkew) + 1;
+    return l + ((kSkewP + 1 - l % kSkewP) % kSkewP);   // round up to 1 mod kSkewP
 }
 
 template <bool INV> __device__ __forceinline__ void dft2(float2* a) {
@@ -153,8 +159,8 @@ __device__ __forceinline__ void build_twiddles(float2* tab, const float2* __rest
 // One Stockham pass, sub-transform size NSUB -> NSUB*RHO, on NS signals
 // v[S0..S0+NS).  Non-final passes write to LDS (signal s at lds + s*ls); the
 // final pass leaves its outputs in registers.  With the skew-16 layout the
-// RHO outputs of a butterfly land at lpad(base) + r*NSUB + (r*NSUB >> 4) for
-// every power-of-two NSUB, so one address per butterfly suffices.  ptab: this
+// RHO outputs of a butterfly land at lpad(base) + r*NSUB + (r*NSUB >> kSkew)
+// for every power-of-two NSUB, so one address per butterfly suffices.  ptab: this
 // pass's twiddle table, entry (r-1)*NSUB + k (unused when NSUB = 1).
 template <int N, int E, int RHO, int NSUB, bool INV, bool LAST, int NS, int S0, int S>
 __device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* ptab, float2* lds, int ls) {
@@ -185,7 +191,7 @@ __device__ __forceinline__ void st_pass(float2 (&v)[S][E], int j, const float2* 
 #pragma unroll
             for (int r = 0; r < RHO; ++r) {
                 if constexpr (LAST) v[S0 + s][q + r * Q] = a[r];
-                else lds[s * ls + wb + r * NSUB + ((r * NSUB) >> 4)] = a[r];
+                else lds[s * ls + wb + r * NSUB + ((r * NSUB) >> kSkew)] = a[r];
             }
         }
     }
@@ -206,7 +212,7 @@ __device__ __forceinline__ void st_passes(float2 (&v)[S][E], int j, const float2
             for (int s = 0; s < NS; ++s)
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
-                    if constexpr (T % 16 == 0) v[S0 + s][m] = lds[s * ls + rb + m * (T + T / 16)];
+                    if constexpr (T % kSkewP == 0) v[S0 + s][m] = lds[s * ls + rb + m * (T + T / kSkewP)];
                     else v[S0 + s][m] = lds[s * ls + lpad(j + T * m)];
                 }
         }
@@ -258,17 +264,16 @@ constexpr int y_NSG(int nz, int Py) { return (Py <= 2048 && nz % 2 == 0) ? 6 : 3
 // ---------------------------------------------------------------------
 // x forward: a block holds R consecutive rows of one signal s.
 // ---------------------------------------------------------------------
-// Body of one x-forward block: logical block lb (tile of R rows of one
-// signal), thread tid < 256, LDS at lds.
+// Rows y0 .. y0+R-1 of signal s (R = x_rows_conc(L) * RPT), thread tid < 256,
+// LDS at lds (x_lds(L, RPT) bytes).
 template <int L, int RPT>
-__device__ __forceinline__ void xfwd_body(const ChainDesc& cd, int S, int ntiles, const float2* __restrict__ tw,
-                                          int lb, int tid, float2* lds) {
+__device__ __forceinline__ void xfwd_rows(const ChainDesc& cd, int S, int s, int y0, const float2* __restrict__ tw,
+                                          int tid, float2* lds) {
     const SweepArgs a = cd.a;
     const float* __restrict__ m = cd.m;
     float2* __restrict__ X = cd.X;
     constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), R = RC * RPT;
     constexpr int LS = lds_len(L);
-    const int s = lb / ntiles, y0 = (lb - s * ntiles) * R;
     const int comp = s / a.nz, z = s - comp * a.nz;
     const int j = tid % T, rg = tid / T;
     // zero padding: hw <= L/2 (L >= 2), so slots n >= L/2 are zero
@@ -332,6 +337,15 @@ __device__ __forceinline__ void xfwd_body(const ChainDesc& cd, int S, int ntiles
         }
     }
 }
+// Body of one x-forward block: logical block lb (tile of R rows of one
+// signal), thread tid < 256, LDS at lds.
+template <int L, int RPT>
+__device__ __forceinline__ void xfwd_body(const ChainDesc& cd, int S, int ntiles, const float2* __restrict__ tw,
+                                          int lb, int tid, float2* lds) {
+    constexpr int R = x_rows_conc(L) * RPT;
+    const int s = lb / ntiles;
+    xfwd_rows<L, RPT>(cd, S, s, (lb - s * ntiles) * R, tw, tid, lds);
+}
 
 template <int L, int RPT, bool BAT>
 __global__ __launch_bounds__(256) void k_xfwd(ChainDesc d0, const ChainDesc* __restrict__ dl, int S, int ntiles,
@@ -348,16 +362,18 @@ __global__ void k_x_twiddles(float2* __restrict__ out, const float2* __restrict_
     build_twiddles<L, x_E(L), 256>(out, tw, threadIdx.x);
 }
 
-// x inverse: mirror of the forward; writes h of colour c when (mask >> c) & 1.
-template <int L, int RPT>
-__device__ __forceinline__ void xinv_body(const ChainDesc& cd, int S, int ntiles, int mask,
-                                          const float2* __restrict__ tw, int lb, int tid, float2* lds) {
+// x inverse, mirror of the forward, for rows y0 .. y0+R-1 of signal s: writes
+// h of colour c when (mask >> c) & 1; TOL: instead writes the field of the
+// cells of colour `mask` to hb[r * hw + n], r = y - y0, n the slot (rows past
+// ny untouched).
+template <int L, int RPT, bool TOL = false>
+__device__ __forceinline__ void xinv_rows(const ChainDesc& cd, int S, int s, int y0, int mask,
+                                          const float2* __restrict__ tw, int tid, float2* lds, float* hb = nullptr) {
     const SweepArgs a = cd.a;
     const float2* __restrict__ X = cd.X;
     float* __restrict__ h = cd.h;
     constexpr int E = x_E(L), T = x_T(L), RC = x_rows_conc(L), R = RC * RPT;
     constexpr int LS = lds_len(L);
-    const int s = lb / ntiles, y0 = (lb - s * ntiles) * R;
     const int comp = s / a.nz, z = s - comp * a.nz;
     const int j = tid % T, rg = tid / T;
     constexpr int WSTEP = TW_N / (2 * L);
@@ -400,19 +416,37 @@ __device__ __forceinline__ void xinv_body(const ChainDesc& cd, int S, int ntiles
         const int y = y0 + rg + RC * i;
         if (y >= a.ny) continue;
         const int ce = (y + z) & 1;
-        const long long ro = ((long long)z * a.ny + y) * a.hw;
-        float* he = h + ((long long)ce * 3 + comp) * a.Nc + ro;
-        float* ho = h + ((long long)(1 - ce) * 3 + comp) * a.Nc + ro;
-        const bool we = (mask >> ce) & 1, wo = (mask >> (1 - ce)) & 1;
         constexpr int QH = E > 1 ? E / 2 : 1;   // slots n < hw <= L/2 only
+        if constexpr (TOL) {
+            // slot n of colour `mask`: x = 2n when the even cells have it, else 2n+1
+            float* hr = hb + (rg + RC * i) * a.hw;
+            const bool ev = ce == mask;
 #pragma unroll
-        for (int q = 0; q < QH; ++q) {
-            const int n = j + T * q;
-            if (n >= a.hw) continue;
-            if (we && 2 * n < a.nx) he[n] = v[i][q].x;
-            if (wo && 2 * n + 1 < a.nx) ho[n] = v[i][q].y;
+            for (int q = 0; q < QH; ++q) {
+                const int n = j + T * q;
+                if (n < a.hw && 2 * n + (ev ? 0 : 1) < a.nx) hr[n] = ev ? v[i][q].x : v[i][q].y;
+            }
+        } else {
+            const long long ro = ((long long)z * a.ny + y) * a.hw;
+            float* he = h + ((long long)ce * 3 + comp) * a.Nc + ro;
+            float* ho = h + ((long long)(1 - ce) * 3 + comp) * a.Nc + ro;
+            const bool we = (mask >> ce) & 1, wo = (mask >> (1 - ce)) & 1;
+#pragma unroll
+            for (int q = 0; q < QH; ++q) {
+                const int n = j + T * q;
+                if (n >= a.hw) continue;
+                if (we && 2 * n < a.nx) he[n] = v[i][q].x;
+                if (wo && 2 * n + 1 < a.nx) ho[n] = v[i][q].y;
+            }
         }
     }
+}
+template <int L, int RPT>
+__device__ __forceinline__ void xinv_body(const ChainDesc& cd, int S, int ntiles, int mask,
+                                          const float2* __restrict__ tw, int lb, int tid, float2* lds) {
+    constexpr int R = x_rows_conc(L) * RPT;
+    const int s = lb / ntiles;
+    xinv_rows<L, RPT>(cd, S, s, (lb - s * ntiles) * R, mask, tw, tid, lds);
 }
 
 template <int L, int RPT, bool BAT>
@@ -917,7 +951,7 @@ __device__ __forceinline__ void y_fwd_mf(float2 (&v)[SH][E], int j, const float2
     for (int s = 0; s < NSG; ++s)
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            if constexpr (T % 16 == 0) v[G + s][m] = lds[s * ls + rb + m * (T + T / 16)];
+            if constexpr (T % kSkewP == 0) v[G + s][m] = lds[s * ls + rb + m * (T + T / kSkewP)];
             else v[G + s][m] = lds[s * ls + lpad(j + T * m)];
         }
     if constexpr (RF > 1)

@@ -123,6 +123,7 @@ __device__ __forceinline__ const ChainDesc& chain_at(const ChainDesc& one, const
 
 int ypass_E(int nz, int Py);                    // elements per thread of the y pass
 int x_rpt_default(int L);                       // x-pass rows per thread without tuning
+size_t x_pass_lds(int L, int rpt);              // LDS bytes of an x-pass block with rpt rows per thread
 bool ypass_split_ok(int nz, int Py);            // split-precision y-pass stages available for this shape
 hipError_t launch_init(const SweepArgs& a, const ClassCoef* ctab, const uint32_t* cid, float* m, int kind,
                        float dx, float dy, float dz, hipStream_t s);
@@ -141,6 +142,13 @@ hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact,
                        int colour, bool stats, int shift, uint8_t* dec, hipStream_t s);
 hipError_t launch_end_sweep(const Chains& c, int shift, long long N, double* series, unsigned long long rec_base,
                             hipStream_t s);
+// Fused colour pass (fused.hip): x-inverse of the field the pass reads, the
+// four-cells-per-thread pass and the x-forward of the updated rows in one
+// kernel; for uniform materials with nx % 8 == 0 and the field refreshed
+// before each colour.
+bool fused_ok(const SweepArgs& a, int L, bool classes);
+hipError_t launch_fused(const SweepArgs& a, const DemagPlan& p, bool exact, bool dmi, const Chains& c, int colour,
+                        int shift, const float2* tw, hipStream_t s);
 hipError_t launch_energy(const SweepArgs& a, bool classes, bool cubic, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out);
 hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s);

@@ -186,6 +186,95 @@ __global__ __launch_bounds__(kAccBins) void k_end_sweep(ChainDesc d0, const Chai
 // C = 4: rows hold a multiple of 4 slots (nx % 8 == 0), uniform material.
 // (single chain: at most 128 VGPRs for four waves per SIMD, measured faster
 // than three; the batched form needs a few more registers for its chain view)
+// Four consecutive cells of colour `colour` in row (y, z), slots 4 ic .. 4 ic + 3
+// (rows hold a multiple of 4 slots).  hp: the frozen field of those slots,
+// component c at hp + c * hcs (float4-aligned; DMG only).  Adds the new
+// m, |m|^2 and accepted moves to the running sums.
+template <bool DMG, bool EXACT, bool DMI>
+__device__ __forceinline__ void pass4_cells(const SweepArgs& a, const ClassCoef& C, float* __restrict__ m, int colour,
+                                            int y, int z, int ic, const float* hp, long long hcs,
+                                            unsigned long long sweep, float omc, uint8_t* __restrict__ dec,
+                                            double& sx, double& sy, double& sz, double& sq,
+                                            unsigned long long& nacc) {
+    const int row = z * a.ny + y;
+    const int par = (colour + y + z) & 1;
+    const int Nc = (int)a.Nc;
+    const int i0 = ic * 4;
+    const int o0 = row * a.hw + i0;
+    float* own = m + colour * 3 * Nc;
+    const float* oth = m + (1 - colour) * 3 * Nc;
+    float4 A[3], O[3], YM[3], YP[3], ZM[3], ZP[3], H[3];
+    float EL[3], ER[3];
+    const bool hy_m = y > 0, hy_p = y + 1 < a.ny, hz_m = z > 0, hz_p = z + 1 < a.nz;
+    const bool el = i0 > 0, er = i0 + 4 < a.hw;
+    // neighbour rows/slots: load from a clamped (always valid) address, zero what is absent
+    const int dym = hy_m ? -a.hw : 0, dyp = hy_p ? a.hw : 0;
+    const int dzm = hz_m ? -a.ny * a.hw : 0, dzp = hz_p ? a.ny * a.hw : 0;
+    const int del = el ? -1 : 0, der = er ? 4 : 3;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float* oc = oth + c * Nc + o0;
+        A[c] = *(const float4*)(own + c * Nc + o0);
+        O[c] = *(const float4*)oc;
+        YM[c] = *(const float4*)(oc + dym);
+        YP[c] = *(const float4*)(oc + dyp);
+        ZM[c] = *(const float4*)(oc + dzm);
+        ZP[c] = *(const float4*)(oc + dzp);
+        EL[c] = oc[del];
+        ER[c] = oc[der];
+        if (DMG) H[c] = *(const float4*)(hp + c * hcs);
+        if (!hy_m) YM[c] = zero4;
+        if (!hy_p) YP[c] = zero4;
+        if (!hz_m) ZM[c] = zero4;
+        if (!hz_p) ZP[c] = zero4;
+        if (!el) EL[c] = 0.f;
+        if (!er) ER[c] = 0.f;
+    }
+    auto comp = [](const float4& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w)); };
+    float4 OUT[3];
+    const int xbase = 2 * i0 + par;
+    const unsigned pbase = (unsigned)((z * a.ny + y) * a.nx + xbase);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = xbase + 2 * k;
+        Nbr nb[6];
+        // x-1: other slot i0+k-1 (par 0) or i0+k (par 1); x+1: i0+k (par 0) or i0+k+1 (par 1)
+        float lx, ly, lz, rx, ry, rz;
+        if (par) {
+            lx = comp(O[0], k); ly = comp(O[1], k); lz = comp(O[2], k);
+            if (k < 3) { rx = comp(O[0], k + 1); ry = comp(O[1], k + 1); rz = comp(O[2], k + 1); }
+            else { rx = ER[0]; ry = ER[1]; rz = ER[2]; }
+        } else {
+            if (k > 0) { lx = comp(O[0], k - 1); ly = comp(O[1], k - 1); lz = comp(O[2], k - 1); }
+            else { lx = EL[0]; ly = EL[1]; lz = EL[2]; }
+            rx = comp(O[0], k); ry = comp(O[1], k); rz = comp(O[2], k);
+        }
+        nb[0] = {lx, ly, lz, x > 0 ? a.wx : 0.f};
+        nb[1] = {rx, ry, rz, x + 1 < a.nx ? a.wx : 0.f};
+        nb[2] = {comp(YM[0], k), comp(YM[1], k), comp(YM[2], k), hy_m ? a.wy : 0.f};
+        nb[3] = {comp(YP[0], k), comp(YP[1], k), comp(YP[2], k), hy_p ? a.wy : 0.f};
+        nb[4] = {comp(ZM[0], k), comp(ZM[1], k), comp(ZM[2], k), hz_m ? a.wz : 0.f};
+        nb[5] = {comp(ZP[0], k), comp(ZP[1], k), comp(ZP[2], k), hz_p ? a.wz : 0.f};
+        const unsigned pnat = pbase + 2u * k;
+        const uint4 r = philox4x32_10(make_uint4(pnat, (uint32_t)sweep, a.chain, (uint32_t)colour), a.k0, a.k1);
+        float ox, oy, oz;
+        const bool ok = cell_move<EXACT, DMI, DMG, false>(a, C, r, omc, comp(A[0], k), comp(A[1], k), comp(A[2], k), nb,
+                                                   DMG ? comp(H[0], k) : 0.f, DMG ? comp(H[1], k) : 0.f,
+                                                   DMG ? comp(H[2], k) : 0.f, ox, oy, oz);
+        if (k == 0) { OUT[0].x = ox; OUT[1].x = oy; OUT[2].x = oz; }
+        if (k == 1) { OUT[0].y = ox; OUT[1].y = oy; OUT[2].y = oz; }
+        if (k == 2) { OUT[0].z = ox; OUT[1].z = oy; OUT[2].z = oz; }
+        if (k == 3) { OUT[0].w = ox; OUT[1].w = oy; OUT[2].w = oz; }
+        if (dec) dec[pnat] = ok ? 1 : 0;
+        nacc += ok ? 1ull : 0ull;
+        sx += ox; sy += oy; sz += oz;
+        sq += (double)ox * ox + (double)oy * oy + (double)oz * oz;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) *(float4*)(own + c * Nc + o0) = OUT[c];
+}
+
 template <bool DMG, bool EXACT, bool DMI>
 __device__ __forceinline__ void pass4_body(const ChainDesc& cd, int colour, int stats, int shift,
                                            uint8_t* __restrict__ dec, int lb, int tid) {
@@ -205,89 +294,13 @@ __device__ __forceinline__ void pass4_body(const ChainDesc& cd, int colour, int 
     unsigned long long nacc = 0;
     if (lr < a.ny * a.nz) {
         const int y = lr / a.nz, z = lr - y * a.nz;
-        const int row = z * a.ny + y;
-        const int par = (colour + y + z) & 1;
-        const int Nc = (int)a.Nc;
-        const int i0 = ic * 4;
-        const int o0 = row * a.hw + i0;
-        float* own = m + colour * 3 * Nc;
-        const float* oth = m + (1 - colour) * 3 * Nc;
-        const unsigned long long sweep = st->sweep;
-        const float omc = st->omc;
-        const ClassCoef C = ctab[0];
-        float4 A[3], O[3], YM[3], YP[3], ZM[3], ZP[3], H[3];
-        float EL[3], ER[3];
-        const bool hy_m = y > 0, hy_p = y + 1 < a.ny, hz_m = z > 0, hz_p = z + 1 < a.nz;
-        const bool el = i0 > 0, er = i0 + 4 < a.hw;
-        // neighbour rows/slots: load from a clamped (always valid) address, zero what is absent
-        const int dym = hy_m ? -a.hw : 0, dyp = hy_p ? a.hw : 0;
-        const int dzm = hz_m ? -a.ny * a.hw : 0, dzp = hz_p ? a.ny * a.hw : 0;
-        const int del = el ? -1 : 0, der = er ? 4 : 3;
-        const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float* oc = oth + c * Nc + o0;
-            A[c] = *(const float4*)(own + c * Nc + o0);
-            O[c] = *(const float4*)oc;
-            YM[c] = *(const float4*)(oc + dym);
-            YP[c] = *(const float4*)(oc + dyp);
-            ZM[c] = *(const float4*)(oc + dzm);
-            ZP[c] = *(const float4*)(oc + dzp);
-            EL[c] = oc[del];
-            ER[c] = oc[der];
-            if (DMG) H[c] = *(const float4*)(h + (colour * 3 + c) * Nc + o0);
-            if (!hy_m) YM[c] = zero4;
-            if (!hy_p) YP[c] = zero4;
-            if (!hz_m) ZM[c] = zero4;
-            if (!hz_p) ZP[c] = zero4;
-            if (!el) EL[c] = 0.f;
-            if (!er) ER[c] = 0.f;
-        }
-        auto comp = [](const float4& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w)); };
-        float4 OUT[3];
-        const int xbase = 2 * i0 + par;
-        const unsigned pbase = (unsigned)((z * a.ny + y) * a.nx + xbase);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int x = xbase + 2 * k;
-            Nbr nb[6];
-            // x-1: other slot i0+k-1 (par 0) or i0+k (par 1); x+1: i0+k (par 0) or i0+k+1 (par 1)
-            float lx, ly, lz, rx, ry, rz;
-            if (par) {
-                lx = comp(O[0], k); ly = comp(O[1], k); lz = comp(O[2], k);
-                if (k < 3) { rx = comp(O[0], k + 1); ry = comp(O[1], k + 1); rz = comp(O[2], k + 1); }
-                else { rx = ER[0]; ry = ER[1]; rz = ER[2]; }
-            } else {
-                if (k > 0) { lx = comp(O[0], k - 1); ly = comp(O[1], k - 1); lz = comp(O[2], k - 1); }
-                else { lx = EL[0]; ly = EL[1]; lz = EL[2]; }
-                rx = comp(O[0], k); ry = comp(O[1], k); rz = comp(O[2], k);
-            }
-            nb[0] = {lx, ly, lz, x > 0 ? a.wx : 0.f};
-            nb[1] = {rx, ry, rz, x + 1 < a.nx ? a.wx : 0.f};
-            nb[2] = {comp(YM[0], k), comp(YM[1], k), comp(YM[2], k), hy_m ? a.wy : 0.f};
-            nb[3] = {comp(YP[0], k), comp(YP[1], k), comp(YP[2], k), hy_p ? a.wy : 0.f};
-            nb[4] = {comp(ZM[0], k), comp(ZM[1], k), comp(ZM[2], k), hz_m ? a.wz : 0.f};
-            nb[5] = {comp(ZP[0], k), comp(ZP[1], k), comp(ZP[2], k), hz_p ? a.wz : 0.f};
-            const unsigned pnat = pbase + 2u * k;
-            const uint4 r = philox4x32_10(make_uint4(pnat, (uint32_t)sweep, a.chain, (uint32_t)colour), a.k0, a.k1);
-            float ox, oy, oz;
-            const bool ok = cell_move<EXACT, DMI, DMG, false>(a, C, r, omc, comp(A[0], k), comp(A[1], k), comp(A[2], k), nb,
-                                                       DMG ? comp(H[0], k) : 0.f, DMG ? comp(H[1], k) : 0.f,
-                                                       DMG ? comp(H[2], k) : 0.f, ox, oy, oz);
-            if (k == 0) { OUT[0].x = ox; OUT[1].x = oy; OUT[2].x = oz; }
-            if (k == 1) { OUT[0].y = ox; OUT[1].y = oy; OUT[2].y = oz; }
-            if (k == 2) { OUT[0].z = ox; OUT[1].z = oy; OUT[2].z = oz; }
-            if (k == 3) { OUT[0].w = ox; OUT[1].w = oy; OUT[2].w = oz; }
-            if (dec) dec[pnat] = ok ? 1 : 0;
-            nacc += ok ? 1ull : 0ull;
-            sx += ox; sy += oy; sz += oz;
-            sq += (double)ox * ox + (double)oy * oy + (double)oz * oz;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) *(float4*)(own + c * Nc + o0) = OUT[c];
+        const long long o0 = (long long)(z * a.ny + y) * a.hw + ic * 4;
+        pass4_cells<DMG, EXACT, DMI>(a, ctab[0], m, colour, y, z, ic, h + colour * 3 * a.Nc + o0, a.Nc, st->sweep,
+                                     st->omc, dec, sx, sy, sz, sq, nacc);
     }
     if (acc) block_stats(sx, sy, sz, sq, nacc, acc, shift, lb, tid);
 }
+
 template <bool DMG, bool EXACT, bool DMI, bool B>
 __global__ __launch_bounds__(256, B ? 3 : 4) void k_pass4(ChainDesc d0, const ChainDesc* __restrict__ dl, int colour, int stats,
                                                int shift, uint8_t* __restrict__ dec) {

@@ -82,7 +82,7 @@ _SIGS = {
     "mmc_demag_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mmc_subsweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "mmc_get_stats": (C.c_int, [C.c_void_p, C.POINTER(mmc_stats)]),
-    "mmc_get_tuning": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mmc_get_tuning": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mmc_take_averages": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "mmc_get_state": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
     "mmc_set_state": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.c_uint64]),
@@ -261,10 +261,11 @@ class Chain:
 
     def sweep_timed(self, n, every=1):
         """n sweeps with per-kernel HIP-event timing of sweeps 0, every, ...:
-        (ms[5], launches[5]) summed over the sampled sweeps, for demag
-        x-forward, demag y-pass, demag x-inverse, colour pass, end of sweep."""
-        ms = np.zeros(5)
-        cnt = np.zeros(5, dtype=np.int32)
+        (ms[6], launches[6]) summed over the sampled sweeps, for demag
+        x-forward, demag y-pass, demag x-inverse, colour pass, end of sweep,
+        fused colour pass (x-inverse, pass, x-forward)."""
+        ms = np.zeros(6)
+        cnt = np.zeros(6, dtype=np.int32)
         _check(lib().mmc_sweep_timed(self._h, int(n), int(every), ms.ctypes.data, cnt.ctypes.data))
         return ms, cnt
 
@@ -305,11 +306,14 @@ class Chain:
 
     def tuning(self):
         """(rows per thread of the x passes (forward, inverse), us per launch of
-        the candidates 1, 2, 4 for each direction)."""
+        the candidates 1, 2, 4 for each direction, fused colour passes on,
+        us per colour of the separate and the fused form)."""
         rpt = np.zeros(2, dtype=np.int32)
         us = np.zeros(6)
-        _check(lib().mmc_get_tuning(self._h, rpt.ctypes.data, us.ctypes.data))
-        return tuple(int(v) for v in rpt), us
+        fz = C.c_int32()
+        fus = np.zeros(2)
+        _check(lib().mmc_get_tuning(self._h, rpt.ctypes.data, us.ctypes.data, C.byref(fz), fus.ctypes.data))
+        return tuple(int(v) for v in rpt), us, bool(fz.value), fus
 
     def get_state(self):
         sw, cd, win = C.c_uint64(), C.c_int32(), C.c_uint64()

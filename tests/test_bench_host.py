@@ -23,8 +23,12 @@ def test_algorithmic_bytes_loop_workload():
     assert bench.algorithmic_bytes(g, True, "demag_xinv") == spec + 6 * N
     assert bench.algorithmic_bytes(g, True, "colour_pass") == 48 * N // 2
     assert bench.algorithmic_bytes(g, False, "colour_pass") == 36 * N // 2
-    per_sweep = 2 * sum(bench.algorithmic_bytes(g, True, k) for k in bench.KINDS)
+    per_sweep = 2 * sum(bench.algorithmic_bytes(g, True, k) for k in bench.KINDS[:5])
     assert abs(per_sweep / N - 324.1) < 0.1
+    # fused colour pass: spectrum in and out, m read once, own colour written
+    assert bench.algorithmic_bytes(g, True, "fused_pass") == 2 * spec + 18 * N
+    fused_sweep = 2 * sum(bench.algorithmic_bytes(g, True, k) for k in ("demag_ypass", "fused_pass"))
+    assert abs(fused_sweep / N - 276.1) < 0.1
 
 
 def test_counted_traffic_follows_sources(tmp_path, monkeypatch):
