@@ -192,7 +192,7 @@ def batched_leg(n_chains=64, sweeps=1000, seed=0):
             "speedup": t_plain / t_batch}
 
 
-def granular_leg(sweeps=60, warmup=5, every=10, seed=0):
+def granular_leg(sweeps=5000, warmup=5, every=100, seed=0):
     """Granular medium (512x512x8 cells of 3 nm; 3-D Voronoi grains of 10 nm
     mean seed spacing; per-grain easy axis within 10 deg of z, Ku 0.7 MJ/m^3,
     Tc ~ N(700 K, 35 K); exchange across grain boundaries x0.1; 600 K; demag
