@@ -302,15 +302,16 @@ def loop_leg(temperatures=(630.0, 770.0), sweeps_per_point=200, seed=0):
     return out
 
 
-def fe_film_leg(sweeps=100, warmup=5, every=10, seed=0):
-    """The granular Fe film with cubic anisotropy (paper Fig. 5 problem, at 8
-    of its 10 layers): per-cell colour pass with grain classes and the cubic
-    term, demag refreshed once per sweep as in the paper.  Cell-updates/s and
-    the HIP-event time of each kernel kind over the sampled sweeps."""
+def fe_film_leg(sweeps=100, warmup=5, every=10, seed=0, nz=10):
+    """The granular Fe film with cubic anisotropy (paper Fig. 5 problem: 400 x
+    400 cells of 2 nm, nz layers, 10 of them in the paper): per-cell colour
+    pass with grain classes and the cubic term, demag refreshed once per sweep
+    as in the paper.  Cell-updates/s and the HIP-event time of each kernel kind
+    over the sampled sweeps."""
     import torch
     from paper_2106_05593_amd import Chain
     p = workloads.FE_FILM
-    grid = p["grid"]
+    grid = (p["grid"][0], p["grid"][1], nz)
     N = int(np.prod(grid))
     gid, ng = workloads.voronoi_grains(grid, p["cell"], p["grain_spacing"], seed=7)
     ch = Chain(grid, p["cell"], Ms0=p["Ms0"], A0=p["A0"], K1=0.0, Tc=p["Tc"], T=p["T"], B=p["B"], demag=True,
@@ -337,7 +338,7 @@ def fe_film_leg(sweeps=100, warmup=5, every=10, seed=0):
             kern[name] = {"launches": int(cnt[k]), "avg_us": round(avg, 3), "alg_bytes": b,
                           "GBs": round(b / (avg * 1e-6) / 1e9, 1)}
     ch.close()
-    return {"workload": "fe_film_400x400x8", "grid": list(grid), "cell_nm": 2, "grains": int(ng),
+    return {"workload": "fe_film_400x400x%d" % nz, "grid": list(grid), "cell_nm": 2, "grains": int(ng),
             "demag_refresh_per_sweep": 1, "sweeps": sweeps, "ms_per_sweep": 1e3 * wall / sweeps,
             "cell_updates_per_s": N * sweeps / wall, "kernels": kern}
 

@@ -65,7 +65,7 @@ typedef enum {
     MMC_ERR_UNSUPPORTED = -6   /* valid request the library does not implement */
 } mmc_status;
 
-typedef struct { int32_t nx, ny, nz; } mmc_grid;          /* each >= 1; nx, ny <= 2048; N <= 2^28; nz <= 8 with demag */
+typedef struct { int32_t nx, ny, nz; } mmc_grid;          /* each >= 1; nx, ny <= 2048; N <= 2^28; nz <= 32 with demag */
 typedef struct { double hx, hy, hz; } mmc_cellsize;       /* metres, > 0 */
 
 /* Mean-field model behind me(T) and chi_par(T). */
@@ -83,7 +83,12 @@ typedef enum {
 
 /* Demag term (Sec. III, Eq. 14) and the precision of its FFT convolution.
  * The tensor spectrum is computed in FP64 and stored in FP32; the x-direction
- * transforms and the layer mixing run in FP32 in every mode.  The split modes
+ * transforms and the layer mixing run in FP32 in every mode.  Layers are
+ * mixed directly (no transform along z), for 1 <= nz <= 32; with more than 8
+ * layers, or when the 3 nz signals of a padded y column do not fit the
+ * one-kernel y pass's registers, the y pass runs as three kernels through a
+ * work buffer of (padded x / 2) * 3 nz * padded y complex FP32 values (same
+ * arithmetic, more HBM traffic).  The split modes
  * run the radix-16 DFT stages of the y-direction transforms on the matrix
  * cores with each operand split into a high and a low 16-bit part and the
  * products hi*hi + hi*lo + lo*hi accumulated in FP32: BF16 parts keep 16

@@ -11,7 +11,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (source, extra defines, object name); the y pass is compiled once per layer count
 UNITS = [("csrc/api.cpp", [], "api.o"), ("csrc/setup.cpp", [], "setup.o"), ("csrc/kernels.hip", [], "kernels.o"), ("csrc/sweep.hip", [], "sweep.o"),
          ("csrc/demag.hip", [], "demag.o"), ("csrc/persist.hip", [], "persist.o"),
-         ("csrc/fused.hip", [], "fused.o")] + \
+         ("csrc/fused.hip", [], "fused.o"), ("csrc/ystage.hip", [], "ystage.o")] + \
         [("csrc/ypass.hip", ["-DMMC_NZ=%d" % k], "ypass_nz%d.o" % k) for k in range(1, 9)]
 
 

@@ -504,10 +504,8 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(run->B[k])) return fail(MMC_ERR_DOMAIN, "field must be finite");
     if (run->demag) {
-        if (grid->nz > 8) return fail(MMC_ERR_UNSUPPORTED, "demag needs nz <= 8");
+        if (grid->nz > ystage_max_nz()) return fail(MMC_ERR_UNSUPPORTED, "demag needs nz <= %d", ystage_max_nz());
         const int Py = pad_pow2(grid->ny, 1);
-        if (3 * grid->nz * ypass_E(grid->nz, Py) > 96)
-            return fail(MMC_ERR_UNSUPPORTED, "demag: padded ny %d with nz %d exceeds the y-pass register budget", Py, grid->nz);
         if (run->demag >= MMC_DEMAG_SPLIT_BF16 && !ypass_split_ok(grid->nz, Py))
             return fail(MMC_ERR_UNSUPPORTED,
                         "split-precision demag needs an even nz and a padded y length of 512, 1024 or 2048 "
@@ -593,7 +591,12 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
             for (float kv : K) p.kmax = std::max(p.kmax, std::fabs(kv));
             if (!alloc((void**)&p.K, sizeof(float) * K.size())) break;
             if (hipMemcpy(p.K, K.data(), sizeof(float) * K.size(), hipMemcpyHostToDevice) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "copy"); break; }
-            if (!alloc((void**)&p.X, sizeof(float2) * (size_t)(p.L + 1) * p.S * grid->ny)) break;
+            // staged y pass (more than 8 layers, or a padded y too long for the
+            // one-kernel pass's registers): its work buffer follows X
+            const size_t xel = (size_t)(p.L + 1) * p.S * grid->ny;
+            const size_t wel = ystage_needed(grid->nz, p.Py) ? (size_t)ystage_work_elems(p.L, p.S, p.Py) : 0;
+            p.woff = wel ? (long long)xel : 0;
+            if (!alloc((void**)&p.X, sizeof(float2) * (xel + wel))) break;
             std::vector<float2> tw(8192);
             for (int j = 0; j < 8192; ++j) tw[j] = make_float2((float)std::cos(-2.0 * kPi * j / 8192), (float)std::sin(-2.0 * kPi * j / 8192));
             if (!alloc((void**)&ctx->d_tw, sizeof(float2) * (8192 + 4096))) break;

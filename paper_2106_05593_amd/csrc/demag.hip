@@ -1,6 +1,7 @@
 // Demag refresh launches: x-direction FFT kernels and the dispatcher of the
 // three stages (kernels and FFT engine in demag_fft.h; the y pass of each
-// layer count is compiled in its own unit, ypass.hip).
+// layer count is compiled in its own unit, ypass.hip; shapes it cannot hold
+// take the staged y pass of ystage.hip).
 #include "demag_fft.h"
 
 namespace mmc {
@@ -87,6 +88,7 @@ static hipError_t launch_x(int stage, const SweepArgs& a, const DemagPlan& p, co
 hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask,
                               const float2* tw, hipStream_t s) {
     if (stage == 0 || stage == 2) return launch_x(stage, a, p, c, colour_mask, tw, s);
+    if (p.woff > 0) return launch_ystage(c, p, a.nz, tw, s);
     switch (a.nz) {
         case 1: return launch_ypass_nz<1>(c, p, tw, s);
         case 2: return launch_ypass_nz<2>(c, p, tw, s);

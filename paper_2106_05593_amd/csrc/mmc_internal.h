@@ -89,6 +89,7 @@ struct DemagPlan {
     int rpt_f = 2, rpt_i = 2;   // x-pass rows per thread (1, 2 or 4), forward and inverse: the tuned tile shape
     int prec;         // y-pass DFT stages: 0 FP32 (vector units), 1 split BF16, 2 split FP16 (matrix cores)
     float kmax;       // largest magnitude in K (bounds for the FP16 scales)
+    long long woff = 0;   // staged y pass: offset (complex elements) of its work buffer after X; 0: one-kernel y pass
 };
 // Everything a sweep-path kernel needs from one chain.  A single chain's is
 // passed by value; for a batch the descriptors of chains of one shape (grid,
@@ -125,12 +126,16 @@ int ypass_E(int nz, int Py);                    // elements per thread of the y 
 int x_rpt_default(int L);                       // x-pass rows per thread without tuning
 size_t x_pass_lds(int L, int rpt);              // LDS bytes of an x-pass block with rpt rows per thread
 bool ypass_split_ok(int nz, int Py);            // split-precision y-pass stages available for this shape
+bool ystage_needed(int nz, int Py);             // the shape needs the staged y pass (nz > 8 or the register budget)
+int ystage_max_nz();                            // most layers the staged y pass mixes
+long long ystage_work_elems(int L, int S, int Py);   // complex elements of its work buffer
 hipError_t launch_init(const SweepArgs& a, const ClassCoef* ctab, const uint32_t* cid, float* m, int kind,
                        float dx, float dy, float dz, hipStream_t s);
 hipError_t launch_to_split(const SweepArgs& a, const float* nat, float* split, hipStream_t s);
 hipError_t launch_from_split(const SweepArgs& a, const float* split, float* nat, hipStream_t s);
 // Sweep-path launches over the chains c, all of one shape (a: host copy of
 // the shared geometry).
+hipError_t launch_ystage(const Chains& c, const DemagPlan& p, int nz, const float2* tw, hipStream_t s);
 hipError_t launch_demag_stage(int stage, const SweepArgs& a, const DemagPlan& p, const Chains& c, int colour_mask,
                               const float2* tw, hipStream_t s);
 // Fills the x transforms' per-pass twiddle tables at tw + 8192 (tw holds

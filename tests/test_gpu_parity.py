@@ -136,7 +136,14 @@ def test_subsweep_decisions_with_demag_field(O, mmc):
                                        ((512, 16, 4), (5e-9, 4e-9, 3e-9)), ((1024, 8, 4), (5e-9,) * 3),
                                        ((600, 12, 1), (4e-9, 4e-9, 2e-9)),
                                        # the batched workload's two-layer grids (y pass of 512 and 1024 points)
-                                       ((256, 256, 2), (5e-9,) * 3), ((512, 512, 2), (5e-9,) * 3)])
+                                       ((256, 256, 2), (5e-9,) * 3), ((512, 512, 2), (5e-9,) * 3),
+                                       # the staged y pass: more than 8 layers (the 10-layer film of the
+                                       # paper's Fe example, up to the 32-layer maximum), and a padded y of
+                                       # 4096 points whose 3 nz signals exceed the one-kernel pass's registers
+                                       ((24, 40, 10), (2e-9,) * 3), ((300, 20, 9), (3e-9, 3e-9, 2e-9)),
+                                       ((40, 30, 16), (3e-9, 3e-9, 2e-9)), ((16, 520, 12), (4e-9, 3e-9, 2e-9)),
+                                       ((12, 20, 32), (2e-9,) * 3), ((8, 1100, 5), (5e-9,) * 3),
+                                       ((5, 3, 11), (4e-9, 4e-9, 2e-9))])
 def test_demag_field_matches_oracle(O, mmc, grid, cell):
     N = int(np.prod(grid))
     ch = mmc.Chain(grid, cell, T=300.0, demag=True, **MAT)

@@ -286,7 +286,7 @@ def test_invalid_inputs(pkg):
         c.demag_field()                 # demag off for this chain
     assert e.value.status == -5
     with pytest.raises(pkg.MMCError) as e:
-        pkg.Chain((8, 8, 9), (5e-9,) * 3, T=300.0, demag=True, **MAT)
+        pkg.Chain((8, 8, 33), (5e-9,) * 3, T=300.0, demag=True, **MAT)   # more layers than the demag mixes
     assert e.value.status == -6
     with pytest.raises(pkg.MMCError) as e:
         pkg.Chain((8, 8, 1), (5e-9,) * 3, T=300.0, cone_deg=181, **MAT)
@@ -415,7 +415,7 @@ def test_x_tile_tuning_same_bits(pkg, grid, monkeypatch):
 
 @pytest.mark.parametrize("grid,kw", [((1024, 20, 4), {}), ((512, 36, 1), {}), ((96, 40, 3), {}),
                                      ((64, 48, 2), dict(lenmove=1, D0=1.5e-3)), ((16, 16, 1), {}),
-                                     ((8, 8, 2), dict(D0=1e-3))])
+                                     ((8, 8, 2), dict(D0=1e-3)), ((64, 40, 10), {})])
 def test_fused_pass_equals_separate_kernels(pkg, grid, kw, monkeypatch):
     """The fused colour pass (x-inverse of the field, the pass and the
     x-forward of the updated rows in one kernel) gives the same state bits as
