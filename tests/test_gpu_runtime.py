@@ -195,6 +195,33 @@ def test_batch_shape_groups_equal_sequential(pkg):
     batch.close()
 
 
+def test_batch_with_staged_demag_equals_sequential(pkg):
+    """Chains whose demag takes the staged y pass (10 and 12 layers; a 4096-point
+    padded y at 5 layers) run batched (two chains of each shape sharing the
+    staged kernels' launches) with two-layer chains, and give the same bits as
+    each chain run alone."""
+    shapes = [((24, 20, 10), (2e-9,) * 3), ((24, 20, 10), (2e-9,) * 3), ((16, 12, 12), (3e-9,) * 3),
+              ((8, 1100, 5), (5e-9,) * 3), ((8, 1100, 5), (5e-9,) * 3), ((40, 24, 2), (4e-9, 4e-9, 3e-9))]
+
+    def make(i):
+        g, c = shapes[i]
+        return pkg.Chain(g, c, T=350.0 + 60.0 * i, B=(0.0, 0.0, 0.2 - 0.08 * i), demag=True, seed=21 + i,
+                         chain_id=i, adapt_every=4, init=1, **MAT)
+    a = [make(i) for i in range(len(shapes))]
+    b = [make(i) for i in range(len(shapes))]
+    batch = pkg.Batch(a)
+    batch.sweep(6)
+    batch.sync()
+    for c in b:
+        c.sweep(6)
+    for ca, cb in zip(a, b):
+        assert np.array_equal(ca.get_m(), cb.get_m())
+        assert ca.get_state() == cb.get_state()
+    batch.close()
+    for c in a + b:
+        c.close()
+
+
 def test_checkpoint_resume_bit_exact(pkg):
     grid = (40, 36, 2)
     kw = dict(T=500.0, B=(0.0, 0.05, 0.2), demag=True, D0=1e-3, seed=11, adapt_every=10, init=1, **MAT)
