@@ -10,10 +10,11 @@
 //      from ny to PY, into W (3 signals per thread group; the kx = 0 group,
 //      which carries the real pair kx = 0 and kx = L packed as X0 + i XL, also
 //      splits the pair as the one-kernel pass does);
-//   2. k_ys_mix: one thread per (kx, ky) bin mixes the 3*nz signals over
-//      layers, H_i(z) = sum_z' sum_j K_ij(z - z') M_j(z'), in place in W (the
-//      bin's tensor values staged in LDS, its inputs in registers, nz a
-//      runtime value up to the template's NZB);
+//   2. k_ys_mixn / k_ys_mix: one thread per (kx, ky) bin mixes the 3*nz
+//      signals over layers, H_i(z) = sum_z' sum_j K_ij(z - z') M_j(z'), in
+//      place in W: for 9..16 layers with nz fixed at compile time (everything
+//      in registers), otherwise with nz a runtime value up to the template's
+//      NZB (the bin's tensor values staged in LDS, its inputs in registers);
 //   3. k_ys_inv: inverse y transform of each column of W (merging the kx = 0
 //      pair back first), cropped to ny, into X.
 // The arithmetic of each step is the one-kernel pass's (same FFT engine, same
@@ -200,6 +201,105 @@ __global__ __launch_bounds__(ys_BT(NZB)) void k_ys_mix(ChainDesc d0, const Chain
     }
 }
 
+// The same mixing with the layer count NZ fixed at compile time (9 <= NZ <= 16):
+// the bin's 6 NZ tensor values and 3 NZ inputs in registers, the pair loop
+// unrolled (the mixing formulas of the one-kernel y pass), each output layer
+// stored as soon as it is summed.  Up to 10 layers the register budget is set
+// for two waves per SIMD (10 layers spill 28 bytes per lane and still run 7 %
+// faster than at one wave); above, one wave (at two, 11 layers spill 164 bytes
+// and more).
+template <int NZ, bool BAT>
+__global__ __launch_bounds__(128, NZ <= 10 ? 2 : 1) void k_ys_mixn(ChainDesc d0, const ChainDesc* __restrict__ dl,
+                                                 const float* __restrict__ K, int L, int PY, long long woff) {
+    const ChainDesc& cd = chain_at<BAT>(d0, dl, blockIdx.y);
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= (long long)L * PY) return;
+    const int kx = (int)(b / PY), ky = (int)(b - (long long)kx * PY);
+    constexpr int S = 3 * NZ;
+    const int HP = PY / 2;
+    float2* __restrict__ W = cd.X + woff + (long long)kx * S * PY + ky;
+    float2 M[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) M[s] = W[(long long)s * PY];
+    float kv[6 * NZ];
+    if (kx == 0 && (ky == 0 || ky == HP)) {
+        // the real pair: diagonal components, kx = 0 on the real part and kx = L on the imaginary part
+        const float* k0 = K + (long long)ky * 6 * NZ;
+        const float* kl = K + ((long long)L * (HP + 1) + ky) * 6 * NZ;
+#pragma unroll
+        for (int t = 0; t < 3 * NZ; ++t) {
+            kv[t] = k0[t];
+            kv[3 * NZ + t] = kl[t];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int zo = 0; zo < NZ; ++zo) {
+                float hr = 0.f, hi = 0.f;
+#pragma unroll
+                for (int zi = 0; zi < NZ; ++zi) {
+                    const int adz = zo >= zi ? zo - zi : zi - zo;
+                    hr += kv[c * NZ + adz] * M[c * NZ + zi].x;
+                    hi += kv[3 * NZ + c * NZ + adz] * M[c * NZ + zi].y;
+                }
+                W[(long long)(c * NZ + zo) * PY] = make_float2(hr, hi);
+            }
+        return;
+    }
+    long long kb;
+    float sy = 1.0f;
+    if (kx != 0) {
+        kb = (long long)kx * (HP + 1) + (ky <= HP ? ky : PY - ky);
+        sy = ky <= HP ? 1.0f : -1.0f;
+    } else {
+        kb = ky <= HP ? ky : (long long)L * (HP + 1) + (PY - ky);
+    }
+    load_bin<NZ>(kv, K + kb * 6 * NZ);
+    // the ky-odd components (xy, yz) carry sy once; the z-odd ones (xz, yz)
+    // take the sign of dz, known at compile time in the unrolled loops
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+        kv[3 * NZ + i] *= sy;
+        kv[5 * NZ + i] *= sy;
+    }
+#pragma unroll
+    for (int zo = 0; zo < NZ; ++zo) {
+        float2 hx = make_float2(0.f, 0.f), hy = hx, hz = hx;
+#pragma unroll
+        for (int zi = 0; zi < NZ; ++zi) {
+            const int dz = zo - zi, adz = dz >= 0 ? dz : -dz;
+            const float kxx = kv[0 * NZ + adz], kyy = kv[1 * NZ + adz], kzz = kv[2 * NZ + adz];
+            const float kxy = kv[3 * NZ + adz];
+            const float kxz = dz >= 0 ? kv[4 * NZ + adz] : -kv[4 * NZ + adz];
+            const float kyz = dz >= 0 ? kv[5 * NZ + adz] : -kv[5 * NZ + adz];
+            const float2 Mx = M[0 * NZ + zi], My = M[1 * NZ + zi], Mz = M[2 * NZ + zi];
+            // xz, yz spectra are imaginary: (i k) M = (-k M.y, k M.x)
+            hx.x += kxx * Mx.x + kxy * My.x - kxz * Mz.y;
+            hx.y += kxx * Mx.y + kxy * My.y + kxz * Mz.x;
+            hy.x += kxy * Mx.x + kyy * My.x - kyz * Mz.y;
+            hy.y += kxy * Mx.y + kyy * My.y + kyz * Mz.x;
+            hz.x += -kxz * Mx.y - kyz * My.y + kzz * Mz.x;
+            hz.y += kxz * Mx.x + kyz * My.x + kzz * Mz.y;
+        }
+        W[(long long)(0 * NZ + zo) * PY] = hx;
+        W[(long long)(1 * NZ + zo) * PY] = hy;
+        W[(long long)(2 * NZ + zo) * PY] = hz;
+    }
+}
+
+template <int NZ>
+static hipError_t launch_mixn(const Chains& c, const DemagPlan& p, long long woff, hipStream_t s) {
+    const long long bins = (long long)p.L * p.Py;
+    const dim3 grid((unsigned)((bins + 127) / 128), c.many ? c.n : 1);
+    if (c.many)
+        hipLaunchKernelGGL((k_ys_mixn<NZ, true>), grid, dim3(128), 0, s, c.one, c.many, (const float*)p.K, p.L, p.Py,
+                           woff);
+    else
+        hipLaunchKernelGGL((k_ys_mixn<NZ, false>), grid, dim3(128), 0, s, c.one, c.many, (const float*)p.K, p.L, p.Py,
+                           woff);
+    return hipGetLastError();
+}
+
 template <int PY>
 static hipError_t launch_cols(bool inv, const Chains& c, const DemagPlan& p, long long woff, const float2* tw,
                               hipStream_t s) {
@@ -260,8 +360,17 @@ hipError_t launch_ystage(const Chains& c, const DemagPlan& p, int nz, const floa
     if (p.woff <= 0 || p.S != 3 * nz || nz < 1 || nz > 32) return hipErrorInvalidValue;
     hipError_t e = launch_cols_py(false, c, p, p.woff, tw, s);
     if (e != hipSuccess) return e;
-    e = nz <= 8 ? launch_mix<8>(c, p, nz, p.woff, s)
-                : (nz <= 16 ? launch_mix<16>(c, p, nz, p.woff, s) : launch_mix<32>(c, p, nz, p.woff, s));
+    switch (nz) {
+        case 9: e = launch_mixn<9>(c, p, p.woff, s); break;
+        case 10: e = launch_mixn<10>(c, p, p.woff, s); break;
+        case 11: e = launch_mixn<11>(c, p, p.woff, s); break;
+        case 12: e = launch_mixn<12>(c, p, p.woff, s); break;
+        case 13: e = launch_mixn<13>(c, p, p.woff, s); break;
+        case 14: e = launch_mixn<14>(c, p, p.woff, s); break;
+        case 15: e = launch_mixn<15>(c, p, p.woff, s); break;
+        case 16: e = launch_mixn<16>(c, p, p.woff, s); break;
+        default: e = nz <= 8 ? launch_mix<8>(c, p, nz, p.woff, s) : launch_mix<32>(c, p, nz, p.woff, s);
+    }
     if (e != hipSuccess) return e;
     return launch_cols_py(true, c, p, p.woff, tw, s);
 }
