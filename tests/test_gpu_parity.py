@@ -143,7 +143,11 @@ def test_subsweep_decisions_with_demag_field(O, mmc):
                                        ((24, 40, 10), (2e-9,) * 3), ((300, 20, 9), (3e-9, 3e-9, 2e-9)),
                                        ((40, 30, 16), (3e-9, 3e-9, 2e-9)), ((16, 520, 12), (4e-9, 3e-9, 2e-9)),
                                        ((12, 20, 32), (2e-9,) * 3), ((8, 1100, 5), (5e-9,) * 3),
-                                       ((5, 3, 11), (4e-9, 4e-9, 2e-9))])
+                                       ((5, 3, 11), (4e-9, 4e-9, 2e-9)),
+                                       # the largest transforms: x length 2048 (nx > 1024) and a 4096-point
+                                       # padded y (ny > 1024) on the one-kernel y pass
+                                       ((1100, 6, 2), (5e-9,) * 3), ((2048, 3, 1), (4e-9, 4e-9, 2e-9)),
+                                       ((16, 1100, 2), (5e-9,) * 3), ((6, 2048, 1), (3e-9,) * 3)])
 def test_demag_field_matches_oracle(O, mmc, grid, cell):
     N = int(np.prod(grid))
     ch = mmc.Chain(grid, cell, T=300.0, demag=True, **MAT)
