@@ -52,6 +52,8 @@ def algorithmic_bytes(grid, demag, kind):
         return per * N // 2
     if kind == "fused_pass":
         return 2 * spec + 12 * N + 6 * N            # spectrum in and out, m read, own colour written
+    if kind == "fused_pass_half":
+        return spec + 12 * N + 6 * N                # spectrum in, m read, own colour written
     return 0
 
 
@@ -436,7 +438,9 @@ def main():
     value = N * args.steps / wall
 
     per_kernel = {}
-    for k, name in enumerate(KINDS):
+    form = ch.tuning()[2]                       # colour-pass form chosen at creation (0, 1 or 2)
+    kinds = KINDS[:5] + (["fused_pass_half"] if form == 2 else ["fused_pass"])
+    for k, name in enumerate(kinds):
         if cnt[k] == 0:
             continue
         avg_us = 1e3 * ms[k] / cnt[k]
@@ -449,7 +453,7 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom), "kernel": dom}
     sampled = (args.steps + args.profile_every - 1) // args.profile_every
     roofline["event_sampled_sweeps"] = sampled
-    sweep_bytes = sum(algorithmic_bytes(grid, True, n) * int(cnt[k]) for k, n in enumerate(KINDS)) / sampled
+    sweep_bytes = sum(algorithmic_bytes(grid, True, n) * int(cnt[k]) for k, n in enumerate(kinds)) / sampled
     out = {
         "metric": "MC cell-updates/s at 1024x1024x4 w/ demag; batched chains/s vs plain, FP32",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -459,6 +463,7 @@ def main():
                    "mu0H_T": wl["B"][2], "demag_refresh_per_sweep": 2, "sweep_alg_bytes_per_cell": round(sweep_bytes / N, 1)},
         "roofline": roofline,
         "kernels": per_kernel,
+        "tuning": {"x_rows_per_thread": list(ch.tuning()[0]), "colour_pass_form": form},
     }
     if not args.no_batched:
         print("bench: batched chains leg", file=sys.stderr, flush=True)

@@ -228,11 +228,12 @@ mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series);
  * sweeps:
  * 0 demag x-forward FFT, 1 demag y-pass (FFT, layer mixing, inverse FFT),
  * 2 demag x-inverse FFT, 3 colour pass, 4 end-of-sweep statistics,
- * 5 fused colour pass (x-inverse of the field, the colour pass and the
- * x-forward of the updated rows in one kernel: chains of uniform material
- * with nx % 8 == 0 and the field refreshed before each colour; a sweep call
- * then starts with one x-forward; MMC_FUSE=0 in the environment at
- * mmc_create keeps the separate kernels for that context). */
+ * 5 fused colour pass (chains of uniform material with nx % 8 == 0 and the
+ * field refreshed before each colour, in the form mmc_get_tuning reports:
+ * form 1, the x-inverse of the field, the colour pass and the x-forward of the
+ * updated rows in one kernel, a sweep call then starting with one x-forward;
+ * form 2, the x-inverse and the colour pass in one kernel, each colour
+ * preceded by an x-forward). */
 mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[6], int32_t launches_out[6]);
 
 /* Total free energy (J) of the current state and its split {exchange (Eq. 10
@@ -304,16 +305,18 @@ mmc_status mmc_take_averages(mmc_ctx* ctx, double avg_out[4], uint64_t* n_out);
  * us_per_launch is not NULL, the measured microseconds per launch of the
  * candidates (forward 1, 2, 4, inverse 1, 2, 4; zeros when not tuned).
  * MMC_TUNE=1, 2 or 4 forces that many rows per thread in both directions.
- * Also decided at mmc_create: whether the colour passes run fused with the
- * x transforms around them (see mmc_sweep_timed, kind 5) or as separate
- * kernels: for chains that allow it, one colour of each form is timed from
- * the state (restored afterwards, so the chain is unchanged; both forms give
- * the same bits), the faster is kept and cached per shape; MMC_FUSE=0 or 1
- * forces the form.  *fused (may be NULL) is 1 when the fused form runs;
- * fuse_us (may be NULL) the timed us per colour of the separate and the
- * fused form (zeros when not timed).  Errors: MMC_ERR_STATE without demag. */
+ * Also decided at mmc_create: the form of the colour passes (see
+ * mmc_sweep_timed, kind 5): 0 separate kernels; 1 fused with the x transforms
+ * on either side of it (x-inverse of the field it reads and x-forward of the
+ * rows it updated); 2 half fused (the x-inverse only; the x-forward stays a
+ * kernel of its own).  For chains that allow it, one colour of each form is
+ * timed from the state (restored afterwards, so the chain is unchanged; all
+ * forms give the same bits), the fastest is kept and cached per shape;
+ * MMC_FUSE=0, 1 or 2 forces a form.  *fused (may be NULL) is the form that
+ * runs; fuse_us (may be NULL) the timed us per colour of forms 0, 1, 2 (zeros
+ * when not timed).  Errors: MMC_ERR_STATE without demag. */
 mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_per_launch[6], int32_t* fused,
-                          double fuse_us[2]);
+                          double fuse_us[3]);
 
 /* Run state for checkpoint/resume: the sweep counter, cone angle and accept
  * window; with the state m (mmc_get_m / mmc_set_m) this restores a chain

@@ -91,8 +91,8 @@ struct mmc_ctx {
     bool demag = false;
     DemagPlan plan{};
     double xtune_us[6] = {0, 0, 0, 0, 0, 0};   // x-pass tuning: us per launch of each candidate
-    int fuse = -1;               // fused colour passes: 1 on, 0 off, -1 not decided (tuned at creation)
-    double fuse_us[2] = {0, 0};  // tuning: us per colour of the separate kernels and of the fused kernel
+    int fuse = -1;               // colour-pass form: 0 separate, 1 fused, 2 half fused, -1 not decided (tuned)
+    double fuse_us[3] = {0, 0, 0};  // tuning: us per colour of the separate, fused and half-fused forms
     float2* d_tw = nullptr;
     SweepArgs args{};
     unsigned long long host_sweep = 0;
@@ -199,7 +199,7 @@ static mmc_status init_state(mmc_ctx* ctx) {
 
 // Launch sequence of n sweeps.  With `prof`, HIP events bracket every launch
 // (kinds: 0 demag x-forward, 1 demag y-pass, 2 demag x-inverse, 3 colour pass,
-// 4 end of sweep, 5 fused x-inverse + colour pass + x-forward).
+// 4 end of sweep, 5 fused x-inverse + colour pass (+ x-forward in the full form)).
 struct LaunchProf {
     std::vector<hipEvent_t> ev;
     std::vector<int> kind;
@@ -207,13 +207,15 @@ struct LaunchProf {
     int every = 1;    // instrument sweeps 0, every, 2*every, ...
 };
 
-// The fused colour pass serves chains of uniform material, nx % 8 == 0 and
-// the field refreshed before each colour; MMC_FUSE=0 in the environment at
-// mmc_create keeps the separate kernels for that context.
-static bool fuse_eligible(const mmc_ctx* c) {
-    return c->demag && c->run.refresh_per_sweep >= 2 && !c->cubic && fused_ok(c->args, c->plan.L, c->has_classes);
+// The fused colour passes serve chains of uniform material, nx % 8 == 0 and
+// the field refreshed before each colour (the half form from a padded x
+// length of 64 on); MMC_FUSE=0, 1 or 2 in the environment at mmc_create
+// forces the separate kernels, the fused or the half-fused form.
+static bool fuse_eligible(const mmc_ctx* c, int form) {
+    return c->demag && c->run.refresh_per_sweep >= 2 && !c->cubic &&
+           fused_ok(c->args, c->plan.L, c->has_classes, form == 1);
 }
-static bool use_fused(const mmc_ctx* c) { return c->fuse == 1 && fuse_eligible(c); }
+static int fused_form(const mmc_ctx* c) { return c->fuse >= 1 && fuse_eligible(c, c->fuse) ? c->fuse : 0; }
 
 // n sweeps of the chains ch, all of c0's shape, on stream st.
 static mmc_status enqueue_core(mmc_ctx* c0, const Chains& ch, int n, hipStream_t st, double* series,
@@ -227,7 +229,28 @@ static mmc_status enqueue_core(mmc_ctx* c0, const Chains& ch, int n, hipStream_t
         return hipEventRecord(prof->ev[prof->used++], st);
     };
     const bool exact = c0->run.lenmove == MMC_LEN_EXACT, dmi = c0->mat.D0 != 0.0;
-    if (n > 0 && use_fused(c0)) {
+    const int form = fused_form(c0);
+    if (n > 0 && form == 2) {
+        // per colour: x-spectrum of the current state, y pass, half-fused pass
+        for (int s = 0; s < n; ++s) {
+            sw = s;
+            for (int c = 0; c < 2; ++c) {
+                for (int stage = 0; stage < 2; ++stage) {
+                    HIPCK(mark(-1));
+                    HIPCK(launch_demag_stage(stage, c0->args, c0->plan, ch, 1 << c, c0->d_tw, st));
+                    HIPCK(mark(stage));
+                }
+                HIPCK(mark(-1));
+                HIPCK(launch_fused(c0->args, c0->plan, exact, dmi, ch, c, c0->fp_shift, c0->d_tw, st, false));
+                HIPCK(mark(5));
+            }
+            HIPCK(mark(-1));
+            HIPCK(launch_end_sweep(ch, c0->fp_shift, c0->N, series, rec_base, st));
+            HIPCK(mark(4));
+        }
+        return MMC_OK;
+    }
+    if (n > 0 && form == 1) {
         // x-spectrum of the current state, then per colour: y pass, fused pass
         // (which leaves the updated state's x-spectrum for the next y pass)
         sw = 0;
@@ -241,7 +264,7 @@ static mmc_status enqueue_core(mmc_ctx* c0, const Chains& ch, int n, hipStream_t
                 HIPCK(launch_demag_stage(1, c0->args, c0->plan, ch, 1 << c, c0->d_tw, st));
                 HIPCK(mark(1));
                 HIPCK(mark(-1));
-                HIPCK(launch_fused(c0->args, c0->plan, exact, dmi, ch, c, c0->fp_shift, c0->d_tw, st));
+                HIPCK(launch_fused(c0->args, c0->plan, exact, dmi, ch, c, c0->fp_shift, c0->d_tw, st, true));
                 HIPCK(mark(5));
             }
             HIPCK(mark(-1));
@@ -361,25 +384,29 @@ static mmc_status tune_x(mmc_ctx* ctx) {
     return MMC_OK;
 }
 
-// Fused or separate colour passes: one colour of each form (x-inverse, colour
-// pass, x-forward against the fused kernel) is timed from the same state,
-// which is restored afterwards (m, run state and statistics accumulators; the
-// spectrum and field buffers are recomputed before every use), and the faster
-// form is kept; the choice is cached per shape.  Both forms give the same bits.
+// Fused or separate colour passes: one colour of each eligible form (x-inverse,
+// colour pass, x-forward; the fused kernel; the half-fused kernel and the
+// x-forward) is timed from the same state, which is restored afterwards (m,
+// run state and statistics accumulators; the spectrum and field buffers are
+// recomputed before every use), and the fastest form is kept; the choice is
+// cached per shape.  All forms give the same bits.
+struct FuseChoice {
+    int form;
+    double us[3];
+};
 static std::mutex g_fuse_mu;
-static std::map<std::string, std::pair<int, std::pair<double, double>>> g_fuse;
+static std::map<std::string, FuseChoice> g_fuse;
 
 static mmc_status tune_fuse(mmc_ctx* ctx) {
-    if (!fuse_eligible(ctx)) { ctx->fuse = 0; return MMC_OK; }
+    if (!fuse_eligible(ctx, 1)) { ctx->fuse = 0; return MMC_OK; }
     char key[96];
     snprintf(key, sizeof key, "%d,%d,%d,%d,%d", ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->run.lenmove, ctx->mat.D0 != 0.0);
     {
         std::lock_guard<std::mutex> lk(g_fuse_mu);
         auto it = g_fuse.find(key);
         if (it != g_fuse.end()) {
-            ctx->fuse = it->second.first;
-            ctx->fuse_us[0] = it->second.second.first;
-            ctx->fuse_us[1] = it->second.second.second;
+            ctx->fuse = it->second.form;
+            std::copy(it->second.us, it->second.us + 3, ctx->fuse_us);
             return MMC_OK;
         }
     }
@@ -406,9 +433,10 @@ static mmc_status tune_fuse(mmc_ctx* ctx) {
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const bool exact = ctx->run.lenmove == MMC_LEN_EXACT, dmi = ctx->mat.D0 != 0.0;
     const Chains one = single(ctx);
-    double us[2] = {0, 0};
+    double us[3] = {0, 0, 0};
     constexpr int kWarm = 1, kTimed = 3;
-    for (int form = 0; form < 2 && e == hipSuccess; ++form) {
+    const int nforms = fuse_eligible(ctx, 2) ? 3 : 2;
+    for (int form = 0; form < nforms && e == hipSuccess; ++form) {
         for (int k = 0; k < kWarm + kTimed && e == hipSuccess; ++k) {
             if (k == kWarm) e = hipEventRecord(e0, ctx->stream);
             if (e != hipSuccess) break;
@@ -418,8 +446,11 @@ static mmc_status tune_fuse(mmc_ctx* ctx) {
                     e = launch_pass(ctx->args, false, true, exact, dmi, false, one, 0, true, ctx->fp_shift, nullptr,
                                     ctx->stream);
                 if (e == hipSuccess) e = launch_demag_stage(0, ctx->args, ctx->plan, one, 3, ctx->d_tw, ctx->stream);
+            } else if (form == 1) {
+                e = launch_fused(ctx->args, ctx->plan, exact, dmi, one, 0, ctx->fp_shift, ctx->d_tw, ctx->stream, true);
             } else {
-                e = launch_fused(ctx->args, ctx->plan, exact, dmi, one, 0, ctx->fp_shift, ctx->d_tw, ctx->stream);
+                e = launch_fused(ctx->args, ctx->plan, exact, dmi, one, 0, ctx->fp_shift, ctx->d_tw, ctx->stream, false);
+                if (e == hipSuccess) e = launch_demag_stage(0, ctx->args, ctx->plan, one, 3, ctx->d_tw, ctx->stream);
             }
         }
         if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
@@ -433,11 +464,13 @@ static mmc_status tune_fuse(mmc_ctx* ctx) {
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(snap);
     if (e != hipSuccess) return fail(MMC_ERR_DEVICE, "fusion tuning: %s", hipGetErrorString(e));
-    ctx->fuse = us[1] < us[0] ? 1 : 0;
-    ctx->fuse_us[0] = us[0];
-    ctx->fuse_us[1] = us[1];
+    int best = 0;
+    for (int f = 1; f < nforms; ++f)
+        if (us[f] < us[best]) best = f;
+    ctx->fuse = best;
+    std::copy(us, us + 3, ctx->fuse_us);
     std::lock_guard<std::mutex> lk(g_fuse_mu);
-    g_fuse[key] = {ctx->fuse, {us[0], us[1]}};
+    g_fuse[key] = {best, {us[0], us[1], us[2]}};
     return MMC_OK;
 }
 
@@ -520,7 +553,7 @@ mmc_status mmc_create(const mmc_grid* grid, const mmc_cellsize* cell, const mmc_
         if (hipGetDevice(&ctx->device) != hipSuccess) { st = fail(MMC_ERR_DEVICE, "no HIP device"); break; }
         {
             const char* fe = getenv("MMC_FUSE");
-            ctx->fuse = (fe && fe[0] == '0') ? 0 : ((fe && fe[0] == '1') ? 1 : -1);
+            ctx->fuse = (fe && fe[0] >= '0' && fe[0] <= '2' && fe[1] == 0) ? fe[0] - '0' : -1;
         }
         // set-up of mmc_energy_noalloc's scratch on this device (once per device)
         {
@@ -905,7 +938,7 @@ mmc_status mmc_subsweep(mmc_ctx* ctx, int32_t colour, const float* h_in, uint8_t
 }
 
 mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_per_launch[6], int32_t* fused,
-                          double fuse_us[2]) {
+                          double fuse_us[3]) {
     mmc_status s = check_live(ctx);
     if (s != MMC_OK) return s;
     if (!rows_per_thread) return fail(MMC_ERR_ARG, "NULL output");
@@ -913,8 +946,8 @@ mmc_status mmc_get_tuning(mmc_ctx* ctx, int32_t rows_per_thread[2], double us_pe
     rows_per_thread[0] = ctx->plan.rpt_f;
     rows_per_thread[1] = ctx->plan.rpt_i;
     if (us_per_launch) std::copy(ctx->xtune_us, ctx->xtune_us + 6, us_per_launch);
-    if (fused) *fused = use_fused(ctx) ? 1 : 0;
-    if (fuse_us) { fuse_us[0] = ctx->fuse_us[0]; fuse_us[1] = ctx->fuse_us[1]; }
+    if (fused) *fused = fused_form(ctx);
+    if (fuse_us) std::copy(ctx->fuse_us, ctx->fuse_us + 3, fuse_us);
     return MMC_OK;
 }
 

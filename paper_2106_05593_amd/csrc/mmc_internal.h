@@ -148,12 +148,13 @@ hipError_t launch_pass(const SweepArgs& a, bool classes, bool demag, bool exact,
 hipError_t launch_end_sweep(const Chains& c, int shift, long long N, double* series, unsigned long long rec_base,
                             hipStream_t s);
 // Fused colour pass (fused.hip): x-inverse of the field the pass reads, the
-// four-cells-per-thread pass and the x-forward of the updated rows in one
-// kernel; for uniform materials with nx % 8 == 0 and the field refreshed
-// before each colour.
-bool fused_ok(const SweepArgs& a, int L, bool classes);
+// four-cells-per-thread pass and (spec) the x-forward of the updated rows in
+// one kernel; for uniform materials with nx % 8 == 0 and the field refreshed
+// before each colour.  Without spec (the half form) the next x-forward runs
+// as its own kernel.
+bool fused_ok(const SweepArgs& a, int L, bool classes, bool spec);
 hipError_t launch_fused(const SweepArgs& a, const DemagPlan& p, bool exact, bool dmi, const Chains& c, int colour,
-                        int shift, const float2* tw, hipStream_t s);
+                        int shift, const float2* tw, hipStream_t s, bool spec);
 hipError_t launch_energy(const SweepArgs& a, bool classes, bool cubic, const ClassCoef* ctab, const uint32_t* cid,
                          const float* m, const float* h, double* part, hipStream_t s, int* nblk_out);
 hipError_t launch_set_cone(DevState* st, int cone_deg, hipStream_t s);

@@ -306,14 +306,14 @@ class Chain:
 
     def tuning(self):
         """(rows per thread of the x passes (forward, inverse), us per launch of
-        the candidates 1, 2, 4 for each direction, fused colour passes on,
-        us per colour of the separate and the fused form)."""
+        the candidates 1, 2, 4 for each direction, colour-pass form (0 separate,
+        1 fused, 2 half fused), us per colour of forms 0, 1, 2)."""
         rpt = np.zeros(2, dtype=np.int32)
         us = np.zeros(6)
         fz = C.c_int32()
-        fus = np.zeros(2)
+        fus = np.zeros(3)
         _check(lib().mmc_get_tuning(self._h, rpt.ctypes.data, us.ctypes.data, C.byref(fz), fus.ctypes.data))
-        return tuple(int(v) for v in rpt), us, bool(fz.value), fus
+        return tuple(int(v) for v in rpt), us, int(fz.value), fus
 
     def get_state(self):
         sw, cd, win = C.c_uint64(), C.c_int32(), C.c_uint64()

@@ -29,6 +29,9 @@ def test_algorithmic_bytes_loop_workload():
     assert bench.algorithmic_bytes(g, True, "fused_pass") == 2 * spec + 18 * N
     fused_sweep = 2 * sum(bench.algorithmic_bytes(g, True, k) for k in ("demag_ypass", "fused_pass"))
     assert abs(fused_sweep / N - 276.1) < 0.1
+    assert bench.algorithmic_bytes(g, True, "fused_pass_half") == spec + 18 * N
+    half_sweep = 2 * sum(bench.algorithmic_bytes(g, True, k) for k in ("demag_xfwd", "demag_ypass", "fused_pass_half"))
+    assert abs(half_sweep / N - 300.1) < 0.1
 
 
 def test_counted_traffic_follows_sources(tmp_path, monkeypatch):

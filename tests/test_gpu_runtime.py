@@ -256,7 +256,7 @@ def test_deterministic_and_record(pkg):
     assert 0 < s[:, 4].max() <= N
 
 
-@pytest.mark.parametrize("fuse", ["0", "1"])
+@pytest.mark.parametrize("fuse", ["0", "1", "2"])
 def test_sweep_timed_sampling(pkg, fuse, monkeypatch):
     """Instrumented sweeps run the same kernels (bitwise same state) and count
     the launches of the sampled sweeps only (separate kernels, and the fused
@@ -269,13 +269,12 @@ def test_sweep_timed_sampling(pkg, fuse, monkeypatch):
     a.sweep(7)
     ms, cnt = b.sweep_timed(7, every=3)           # sweeps 0, 3, 6 instrumented
     assert np.array_equal(a.get_m(), b.get_m()) and a.get_state() == b.get_state()
-    if fuse == "0":
-        assert list(cnt) == [6, 6, 6, 6, 3, 0]
-    else:
-        assert list(cnt) == [1, 6, 0, 0, 3, 6]
+    expect = {"0": ([6, 6, 6, 6, 3, 0], [4, 4, 4, 4, 2, 0]), "1": ([1, 6, 0, 0, 3, 6], [1, 4, 0, 0, 2, 4]),
+              "2": ([6, 6, 0, 0, 3, 6], [4, 4, 0, 0, 2, 4])}[fuse]
+    assert list(cnt) == expect[0]
     assert np.all(ms[cnt > 0] > 0)
     ms1, cnt1 = b.sweep_timed(2)
-    assert list(cnt1) == ([4, 4, 4, 4, 2, 0] if fuse == "0" else [1, 4, 0, 0, 2, 4])
+    assert list(cnt1) == expect[1]
     with pytest.raises(pkg.MMCError) as e:
         b.sweep_timed(2, every=0)
     assert e.value.status == -1
@@ -440,33 +439,45 @@ def test_x_tile_tuning_same_bits(pkg, grid, monkeypatch):
     tuned.close()
 
 
+@pytest.mark.parametrize("form", ["1", "2"])
 @pytest.mark.parametrize("grid,kw", [((1024, 20, 4), {}), ((512, 36, 1), {}), ((96, 40, 3), {}),
                                      ((64, 48, 2), dict(lenmove=1, D0=1.5e-3)), ((16, 16, 1), {}),
-                                     ((8, 8, 2), dict(D0=1e-3)), ((64, 40, 10), {})])
-def test_fused_pass_equals_separate_kernels(pkg, grid, kw, monkeypatch):
-    """The fused colour pass (x-inverse of the field, the pass and the
-    x-forward of the updated rows in one kernel) gives the same state bits as
-    the separate kernels, sweep after sweep; the accepted-move counts agree and
-    the FP64 means agree to rounding (their per-block bins follow the tiles)."""
+                                     ((8, 8, 2), dict(D0=1e-3)), ((64, 40, 10), {}), ((2048, 6, 1), {}),
+                                     ((40, 33, 2), {})])
+def test_fused_pass_equals_separate_kernels(pkg, grid, kw, form, monkeypatch):
+    """The fused colour pass (form 1: x-inverse of the field, the pass and the
+    x-forward of the updated rows in one kernel; form 2: x-inverse and pass in
+    one kernel, the x-forward separate) gives the same state bits as the
+    separate kernels, sweep after sweep; the accepted-move counts agree and the
+    FP64 means agree to rounding (their per-block bins follow the tiles).
+    Shapes the half form does not serve (padded x below 64) run separate."""
     N = int(np.prod(grid))
     m = workloads.random_state(N, seed=N % 97)
     chains = {}
-    for fuse in ("1", "0"):
+    for fuse in (form, "0"):
         monkeypatch.setenv("MMC_FUSE", fuse)
         ch = pkg.Chain(grid, (4e-9, 4e-9, 3e-9), T=520.0, B=(0.01, 0.0, 0.2), demag=True, seed=13, **MAT, **kw)
         ch.set_m(m)
         ch.sweep(2)
         ch.sweep(1)
         chains[fuse] = ch
-    a, b = chains["1"], chains["0"]
+    a, b = chains[form], chains["0"]
     assert np.array_equal(a.get_m(), b.get_m())
     sa, sb = a.stats(), b.stats()
     assert sa["sweeps"] == sb["sweeps"] == 3 and sa["accepts_last"] == sb["accepts_last"]
     assert abs(sa["m2_mean"] - sb["m2_mean"]) <= 1e-13 * abs(sb["m2_mean"])
     ms_a, cnt_a = a.sweep_timed(2)
     ms_b, cnt_b = b.sweep_timed(2)
-    print(grid, "launches fused", cnt_a.tolist(), "separate", cnt_b.tolist(), flush=True)
-    assert cnt_a[5] == 4 and cnt_a[2] == 0 and cnt_a[3] == 0 and cnt_a[0] == 1
+    got = a.tuning()[2]
+    print(grid, "form", got, "launches", cnt_a.tolist(), "separate", cnt_b.tolist(), flush=True)
+    Px = 2
+    while Px < 2 * grid[0] - 1:
+        Px *= 2
+    assert got == (0 if form == "2" and Px < 64 else int(form))
+    if got == 1:
+        assert cnt_a[5] == 4 and cnt_a[2] == 0 and cnt_a[3] == 0 and cnt_a[0] == 1
+    elif got == 2:
+        assert cnt_a[5] == 4 and cnt_a[2] == 0 and cnt_a[3] == 0 and cnt_a[0] == 4 and cnt_a[1] == 4
     assert cnt_b[5] == 0 and cnt_b[3] == 4
     assert np.array_equal(a.get_m(), b.get_m())
     a.close()
@@ -481,11 +492,11 @@ def test_fusion_tuning_keeps_the_state(pkg, monkeypatch):
     monkeypatch.delenv("MMC_FUSE", raising=False)
     a = pkg.Chain(grid, (5e-9,) * 3, T=480.0, B=(0, 0, 0.1), demag=True, seed=4, init=1, **MAT)
     rpt, us, fused, fus = a.tuning()
-    print("fused" if fused else "separate", "us per colour (separate, fused):", fus, flush=True)
-    assert fus[0] > 0 and fus[1] > 0
+    print("form", fused, "us per colour (separate, fused, half fused):", fus, flush=True)
+    assert fus[0] > 0 and fus[1] > 0 and fus[2] > 0 and fused == int(np.argmin(fus))
     monkeypatch.setenv("MMC_FUSE", "0")
     b = pkg.Chain(grid, (5e-9,) * 3, T=480.0, B=(0, 0, 0.1), demag=True, seed=4, init=1, **MAT)
-    assert not b.tuning()[2]
+    assert b.tuning()[2] == 0
     a.sweep(3)
     b.sweep(3)
     assert np.array_equal(a.get_m(), b.get_m())
