@@ -6,7 +6,7 @@
 // the layer mixing needs no memory round trip.  Here the three steps are
 // separate kernels that meet in a work buffer W (complex, [kx][s][PY], after
 // the x-spectrum X in the same allocation):
-//   1. k_ys_fwd: forward y transform of each (kx, s) column of X, zero-padded
+//   1. k_ys_col<PY, false>: forward y transform of each (kx, s) column of X, zero-padded
 //      from ny to PY, into W (3 signals per thread group; the kx = 0 group,
 //      which carries the real pair kx = 0 and kx = L packed as X0 + i XL, also
 //      splits the pair as the one-kernel pass does);
@@ -15,7 +15,7 @@
 //      place in W: for 9..16 layers with nz fixed at compile time (everything
 //      in registers), otherwise with nz a runtime value up to the template's
 //      NZB (the bin's tensor values staged in LDS, its inputs in registers);
-//   3. k_ys_inv: inverse y transform of each column of W (merging the kx = 0
+//   3. k_ys_col<PY, true>: inverse y transform of each column of W (merging the kx = 0
 //      pair back first), cropped to ny, into X.
 // The arithmetic of each step is the one-kernel pass's (same FFT engine, same
 // mixing formulas and tensor layout); only the order of memory traffic
