@@ -390,6 +390,8 @@ def main():
     ap.add_argument("--no-fe-film", action="store_true")
     ap.add_argument("--no-profile-leg", action="store_true")
     ap.add_argument("--no-granular", action="store_true")
+    ap.add_argument("--granular-sweeps", type=int, default=5000,
+                    help="sweeps per precision in the granular leg")
     ap.add_argument("--no-dmi-film", action="store_true")
     ap.add_argument("--loop-leg", action="store_true", help="also run the whole 401-point loop at 630 K and 770 K")
     ap.add_argument("--profile-every", type=int, default=10,
@@ -476,7 +478,7 @@ def main():
         out["temperature_profile"] = profile_leg()
     if not args.no_granular:
         print("bench: granular 512x512x8 leg (FP32 and split demag stages)", file=sys.stderr, flush=True)
-        out["granular"] = granular_leg()
+        out["granular"] = granular_leg(sweeps=args.granular_sweeps)
     if not args.no_dmi_film:
         print("bench: DMI film leg", file=sys.stderr, flush=True)
         out["dmi_film"] = dmi_film_leg()
