@@ -9,15 +9,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "libmmc_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = SO, sanitize: bool = False) -> str:
+    """Compile the oracle into `out`; sanitize: with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only; errors abort), for the
+    sanitizer test."""
     src = os.path.join(HERE, "mmc_oracle.c")
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wno-unknown-pragmas",
-           "-o", SO + ".tmp", src, "-lm"]
+    opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+    cmd = ["gcc"] + opt + ["-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wno-unknown-pragmas",
+                           "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(SO + ".tmp", SO)
-    return SO
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
