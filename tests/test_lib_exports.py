@@ -57,3 +57,20 @@ def test_missing_library_fails_loudly(monkeypatch):
         mmc.lib()
     with pytest.raises(ImportError):
         mmc.Chain((4, 4, 1), (5e-9,) * 3, Ms0=1e6, A0=1e-11, K1=0.0, Tc=700.0, T=300.0)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/mmc.h compiles as strict C99 (and as C++): the ABI takes plain
+    C types only."""
+    import shutil
+    import subprocess
+    import pytest
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "use.c"
+    src.write_text('#include "mmc.h"\nint main(void) { mmc_ctx* c = 0; mmc_stats st; (void)c; (void)st; return 0; }\n')
+    inc = os.path.join(ROOT, "include")
+    for cmd in (["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-I", inc, str(src)],
+                ["g++", "-std=c++17", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", "-I", inc, str(src)]):
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
