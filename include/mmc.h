@@ -213,8 +213,14 @@ mmc_status mmc_get_m(mmc_ctx* ctx, float* out, int on_device);
  * cell of the colour one trial move (cone rotation, length change) accepted
  * by Eq. 5; then reduce the sweep's statistics (FP64), adapt the cone every
  * adapt_every sweeps (Sec. II) and advance the sweep counter, all on the
- * device.  Errors: MMC_ERR_ARG for n < 0, MMC_ERR_STATE after a device
- * error, MMC_ERR_DEVICE from a launch. */
+ * device.  For n >= 16 the launches of 16 sweeps are captured once as a HIP
+ * graph on the context's stream (again after a setter changed kernel
+ * arguments) and replayed, the rest launched directly: the same kernels in
+ * the same order, so the same result bits; MMC_SWEEP_GRAPH=0 in the
+ * environment keeps direct launches, and so does a call made while the
+ * caller captures the context's stream (the sweeps go into that capture).
+ * Errors: MMC_ERR_ARG for n < 0, MMC_ERR_STATE after a device
+ * error, MMC_ERR_DEVICE from a launch or a failed capture. */
 mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n);
 /* As mmc_sweep, and copies per-sweep statistics to host `series` (n*5 doubles:
  * <mx>, <my>, <mz>, <|m|^2> (FP64 reductions) and the accepted-move count). */

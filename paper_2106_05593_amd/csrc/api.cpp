@@ -97,6 +97,10 @@ struct mmc_ctx {
     SweepArgs args{};
     unsigned long long host_sweep = 0;
     unsigned version = 0;        // bumps when kernel arguments change
+    // mmc_sweep's graph of kSweepGraph sweeps, captured at `sg_version`
+    hipGraph_t sg_graph = nullptr;
+    hipGraphExec_t sg_exec = nullptr;
+    unsigned sg_version = 0;
 };
 
 // Chains of one shape advance together: one launch per kernel serves all of
@@ -180,6 +184,7 @@ static mmc_status upload_classes(mmc_ctx* ctx) {
     }
     if (ctx->d_ctab) { HIPCK(hipFree(ctx->d_ctab)); ctx->d_ctab = nullptr; }
     HIPCK(hipMalloc(&ctx->d_ctab, sizeof(ClassCoef) * ctx->nclass));
+    ctx->version++;              // graphs captured before hold the old table's address
     HIPCK(hipMemcpyAsync(ctx->d_ctab, ctx->ctab.data(), sizeof(ClassCoef) * ctx->nclass, hipMemcpyHostToDevice,
                          ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
@@ -506,6 +511,8 @@ void mmc_destroy(mmc_ctx* ctx) {
                     ctx->d_epart, ctx->d_series, ctx->plan.X, ctx->plan.K, ctx->d_tw};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    if (ctx->sg_exec) (void)hipGraphExecDestroy(ctx->sg_exec);
+    if (ctx->sg_graph) (void)hipGraphDestroy(ctx->sg_graph);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -803,11 +810,46 @@ mmc_status mmc_get_m(mmc_ctx* ctx, float* out, int on_device) {
     return MMC_OK;
 }
 
+// Sweep calls of at least kSweepGraph sweeps replay a HIP graph of
+// kSweepGraph sweeps' launches (captured from the chain's stream once, and
+// again after any change of kernel arguments), then enqueue the rest
+// directly: the same kernels in the same order, so the same bits, without the
+// host's per-launch cost, which bounds small chains (a sweep is five to nine
+// launches).  MMC_SWEEP_GRAPH=0 in the environment at mmc_sweep keeps direct
+// launches.
+static constexpr int kSweepGraph = 16;
+
+static mmc_status sweep_graph_ready(mmc_ctx* ctx) {
+    if (ctx->sg_exec && ctx->sg_version == ctx->version) return MMC_OK;
+    if (ctx->sg_exec) { (void)hipGraphExecDestroy(ctx->sg_exec); ctx->sg_exec = nullptr; }
+    if (ctx->sg_graph) { (void)hipGraphDestroy(ctx->sg_graph); ctx->sg_graph = nullptr; }
+    HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    const mmc_status st = enqueue_core(ctx, single(ctx), kSweepGraph, ctx->stream, nullptr, 0, nullptr);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
+    if (st != MMC_OK) { if (gr) (void)hipGraphDestroy(gr); return st; }
+    HIPCK(e);
+    ctx->sg_graph = gr;
+    HIPCK(hipGraphInstantiate(&ctx->sg_exec, ctx->sg_graph, nullptr, nullptr, 0));
+    ctx->sg_version = ctx->version;
+    return MMC_OK;
+}
+
 mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n) {
     mmc_status s = check_live(ctx);
     if (s != MMC_OK) return s;
     if (n < 0) return fail(MMC_ERR_ARG, "negative sweep count");
-    return enqueue_sweeps(ctx, n, nullptr, 0);
+    const char* env = getenv("MMC_SWEEP_GRAPH");
+    if (n < kSweepGraph || (env && env[0] == '0')) return enqueue_sweeps(ctx, n, nullptr, 0);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCK(hipStreamIsCapturing(ctx->stream, &cap));
+    if (cap != hipStreamCaptureStatusNone) return enqueue_sweeps(ctx, n, nullptr, 0);   // into the caller's capture
+    s = sweep_graph_ready(ctx);
+    if (s != MMC_OK) return s;
+    const int reps = n / kSweepGraph;
+    for (int r = 0; r < reps; ++r) HIPCK(hipGraphLaunch(ctx->sg_exec, ctx->stream));
+    ctx->host_sweep += (unsigned long long)reps * kSweepGraph;
+    return enqueue_sweeps(ctx, n - reps * kSweepGraph, nullptr, 0);
 }
 
 mmc_status mmc_sweep_timed(mmc_ctx* ctx, int32_t n, int32_t every, double ms_out[6], int32_t launches_out[6]) {
@@ -852,8 +894,13 @@ mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series) {
         HIPCK(hipMalloc(&ctx->d_series, sizeof(double) * 5 * (size_t)n));
         ctx->series_cap = n;
     }
-    const unsigned long long base = ctx->host_sweep;
-    s = enqueue_sweeps(ctx, n, ctx->d_series, base);
+    // rows are indexed by the device's sweep counter minus its value now (read
+    // back rather than tracked on the host: graphs the caller replays advance it)
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    DevState hs{};
+    HIPCK(hipMemcpy(&hs, ctx->d_st, sizeof hs, hipMemcpyDeviceToHost));
+    ctx->host_sweep = hs.sweep;
+    s = enqueue_sweeps(ctx, n, ctx->d_series, hs.sweep);
     if (s != MMC_OK) return s;
     HIPCK(hipMemcpyAsync(series, ctx->d_series, sizeof(double) * 5 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));

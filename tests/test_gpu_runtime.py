@@ -503,3 +503,112 @@ def test_fusion_tuning_keeps_the_state(pkg, monkeypatch):
     assert a.stats()["accepts_last"] == b.stats()["accepts_last"]
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("fuse,kw", [("0", {}), ("1", {}), ("2", {}), ("auto", dict(D0=1.5e-3, lenmove=1)),
+                                     ("auto", dict(demag=False)), ("auto", dict(refresh_per_sweep=1))])
+def test_sweep_graph_replay_equals_direct(pkg, fuse, kw, monkeypatch):
+    """Sweep calls of 16 sweeps or more replay a captured graph of 16 sweeps
+    and launch the rest directly.  A chain run that way equals one advanced by
+    direct launches only (MMC_SWEEP_GRAPH=0), bit for bit: over several
+    replays with getters, energies and a checkpoint restore in between, and
+    after every setter that changes kernel arguments or reallocates the class
+    table (field, temperature, grains, grain temperatures, cubic anisotropy),
+    each of which must recapture the graph."""
+    if fuse == "auto":
+        monkeypatch.delenv("MMC_FUSE", raising=False)
+    else:
+        monkeypatch.setenv("MMC_FUSE", fuse)
+    grid, cell = (64, 40, 2), (4e-9, 4e-9, 3e-9)
+    N = int(np.prod(grid))
+    args = dict(T=520.0, B=(0.01, 0.0, 0.2), demag=True, seed=21, init=1, adapt_every=8, **MAT)
+    args.update(kw)
+    a = pkg.Chain(grid, cell, **args)
+    b = pkg.Chain(grid, cell, **args)
+    print("form", a.tuning()[2] if args["demag"] else None, kw, flush=True)
+
+    def both(f):
+        monkeypatch.delenv("MMC_SWEEP_GRAPH", raising=False)
+        f(a)
+        monkeypatch.setenv("MMC_SWEEP_GRAPH", "0")
+        f(b)
+        monkeypatch.delenv("MMC_SWEEP_GRAPH", raising=False)
+
+    def same(tag):
+        print(tag, flush=True)
+        assert np.array_equal(a.get_m(), b.get_m()), tag
+        assert a.get_state() == b.get_state(), tag
+        assert a.stats() == b.stats(), tag
+
+    def same_energy():
+        ea_, eb_ = a.energy(), b.energy()
+        assert ea_[0] == eb_[0] and np.array_equal(ea_[1], eb_[1])
+
+    both(lambda c: c.sweep(37))                   # capture, two replays, five direct
+    same("37")
+    same_energy()
+    both(lambda c: c.sweep(16))
+    same("16")
+    st = a.get_state()
+    both(lambda c: c.set_state(st[0] + 5, 17, st[2]))
+    both(lambda c: c.sweep(20))
+    same("restored")
+    both(lambda c: c.set_field((0.0, 0.05, -0.1)))
+    both(lambda c: c.sweep(40))
+    same("field")
+    both(lambda c: c.set_temperature(600.0))
+    both(lambda c: c.sweep(20))
+    same("temperature")
+    rng = np.random.default_rng(3)
+    ng = 5
+    gid = (np.arange(N) // 97) % ng
+    ea = rng.normal(size=(ng, 3))
+    K1, K2, Tc = rng.uniform(1e5, 6e5, ng), np.zeros(ng), rng.uniform(650.0, 720.0, ng)
+    both(lambda c: c.set_grains(gid, ea, K1, K2, Tc, 0.7))
+    both(lambda c: c.sweep(33))
+    same("grains")
+    Tg = rng.uniform(500.0, 620.0, ng)
+    both(lambda c: c.set_grain_temperatures(Tg))
+    both(lambda c: c.sweep(16))
+    same("grain temperatures")
+    axes = np.stack([np.eye(3)[[0, 1]] for _ in range(ng)])
+    both(lambda c: c.set_anisotropy("cubic", axes, K1=-4e4, K2=1e4))
+    both(lambda c: c.sweep(18))
+    same("cubic")
+    same_energy()
+    a.close()
+    b.close()
+
+
+def test_sweep_inside_caller_capture(pkg):
+    """A sweep call made while the caller captures the chain's stream (here a
+    torch CUDA graph) launches its sweeps into that capture instead of
+    capturing a graph of its own; every replay of the caller's graph equals
+    the same sweeps launched directly, with eager getters between replays,
+    and a per-sweep record taken afterwards lands in its own rows."""
+    s = torch.cuda.Stream()
+    grid, cell = (64, 40, 2), (4e-9, 4e-9, 3e-9)
+    kw = dict(T=520.0, B=(0.01, 0.0, 0.2), demag=True, seed=8, init=1, adapt_every=8, **MAT)
+    a = pkg.Chain(grid, cell, stream=s.cuda_stream, **kw)
+    b = pkg.Chain(grid, cell, **kw)
+    a.sweep(2)
+    b.sweep(2)
+    a.sync()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        a.sweep(20)
+    for r in range(3):
+        with torch.cuda.stream(s):
+            g.replay()
+        s.synchronize()
+        b.sweep(20)
+        print("replay", r, flush=True)
+        assert np.array_equal(a.get_m(), b.get_m())
+        assert a.get_state() == b.get_state() and a.stats() == b.stats()
+    # the per-sweep record indexes its rows from the device's sweep counter,
+    # which the caller's replays advanced without the library seeing them
+    ra, rb = a.sweep_record(17), b.sweep_record(17)
+    assert ra.shape == (17, 5) and np.array_equal(ra, rb)
+    assert a.get_state()[0] == 2 + 3 * 20 + 17
+    a.close()
+    b.close()
