@@ -5,13 +5,15 @@ m^2 exp(-F(m)/kT).  With exchange, DMI and demag off every cell is an
 independent chain (a macrospin), so averages can be checked against 2-D
 quadrature.  In the exact length mode (log-uniform factor, exponent 3) the
 chain samples that law exactly; in the paper's mode (uniform factor,
-exponent 4, Eq. 5) only to leading order in sigma, and the residual bias is
-reported and bounded.  The fitted me, chi of the length histogram recover the
+exponent 4, Eq. 5) it does not, and for a length-only F the law it does
+sample is computed from its transition kernel and checked.  The fitted me, chi of the length histogram recover the
 inputs (the paper's Fig. 2 procedure).
 """
 import numpy as np
 import pytest
+from scipy import sparse
 from scipy.optimize import minimize
+from scipy.sparse.linalg import spsolve
 
 KB = 1.380649e-23
 
@@ -79,6 +81,93 @@ def test_macrospin_paper_mode_bias_is_small(oracle_mod, t):
     _, m2_q = quadrature(S, K1, Bz)
     m2, se = batch_se((snap**2).sum(axis=1).mean(axis=1))
     assert abs(m2 / m2_q - 1) < 0.02 + 4 * se / m2_q
+
+
+def length_chain_m2(c, mode, hu, nsub=4, ng=4):
+    """<m^2> of the stationary law of one macrospin's length chain with F
+    depending on the length only (no anisotropy, field or coupling, so the
+    rotation in the cone does not enter the acceptance).  A trial length is
+    L' = f L with f uniform in [1 - sigma, 1 + sigma] and exponent k = 4 (the
+    paper's rule, Eq. 5; mode 0) or ln f uniform in +-ln(1 + sigma) and k = 3
+    (mode 1), accepted with min{1, f^k exp(-dF/kT)}.  The balance equation
+    pi = pi P of the transition kernel P is solved on a grid uniform in
+    u = ln L (where the move is a shift of fixed width): P[i, j] averages over
+    Gauss points of bin i the acceptance-weighted proposal mass that lands in
+    bin j, the rest of each row stays; pi is the null vector of P^T - I,
+    normalised."""
+    def fkT(L):
+        q = L * L
+        return c["la"] * (q - c["me"] ** 2) ** 2 if c["below"] else c["lb"] * q + c["lbc"] * q * q
+    uu = np.linspace(-30.0, 1.0, 600001)
+    lw = 3 * uu - fkT(np.exp(uu))                 # Eq. 1 in u: L^2 e^{-F/kT} dL = L^3 e^{-F/kT} du
+    w = np.exp(lw - lw.max())
+    a, b = uu[w > 1e-16].min(), uu[w > 1e-16].max()
+    sig, k = c["sigma"], (4.0 if mode == 0 else 3.0)
+    dlo, dhi = (np.log1p(-sig), np.log1p(sig)) if mode == 0 else (-np.log1p(sig), np.log1p(sig))
+    n = int(np.ceil((b - a) / hu))
+    edges = a + hu * np.arange(n + 1)
+    xs, ws = np.polynomial.legendre.leggauss(nsub)
+    xg, wg = np.polynomial.legendre.leggauss(ng)
+    D = int(np.ceil(max(-dlo, dhi) / hu)) + 2
+    i = np.arange(n)
+    rows, cols, vals = [], [], []
+    for d in range(-D, D + 1):
+        j = i + d
+        ok = (j >= 0) & (j < n)
+        ii, jj = i[ok], j[ok]
+        mass = np.zeros(ii.size)
+        for sx, sw in zip(xs, ws):
+            u = edges[ii] + 0.5 * hu * (1 + sx)
+            x0 = np.maximum(edges[jj], u + dlo)
+            ell = np.clip(np.minimum(edges[jj + 1], u + dhi) - x0, 0.0, None)
+            for gx, gw in zip(xg, wg):
+                x = x0 + 0.5 * ell * (1 + gx)
+                alpha = np.exp(np.minimum(k * (x - u) - (fkT(np.exp(x)) - fkT(np.exp(u))), 0.0))
+                dens = np.exp(x - u) / (2 * sig) if mode == 0 else 1.0 / (dhi - dlo)   # proposal density in u'
+                mass += 0.5 * sw * 0.5 * ell * gw * alpha * dens
+        rows.append(ii)
+        cols.append(jj)
+        vals.append(mass)
+    P = sparse.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    stay = 1.0 - (np.asarray(P.sum(axis=1)).ravel() - P.diagonal())
+    P = P - sparse.diags(P.diagonal()) + sparse.diags(stay)
+    A = (P.T - sparse.identity(n)).tolil()
+    A[n - 1, :] = 1.0
+    rhs = np.zeros(n)
+    rhs[-1] = 1.0
+    pi = spsolve(A.tocsc(), rhs)
+    e2 = (np.exp(2 * edges[1:]) - np.exp(2 * edges[:-1])) / (2 * hu)     # mean of L^2 = e^{2u} over each bin
+    eq1 = np.trapezoid(w * np.exp(2 * uu), uu) / np.trapezoid(w, uu)
+    return float(pi @ e2), float(eq1)
+
+
+def test_macrospin_paper_mode_samples_its_own_stationary_law(oracle_mod):
+    """The paper's length rule (uniform factor, exponent 4) does not sample
+    Eq. 1 exactly; what it samples follows from its transition kernel.  For
+    isotropic macrospins (3 nm cells, K = H = 0, 0.9 Tc) the kernel's
+    stationary law, solved numerically, predicts <m^2>: the solver is pinned by
+    the exact mode's kernel, which must give back the Eq. 1 quadrature, and
+    the oracle's paper-mode chain must land on the prediction, which lies well
+    outside its error from the Eq. 1 value."""
+    from paper_2106_05593_amd.hysteresis import blocked_se
+    Tc, t = 700.0, 0.9
+    S = oracle_mod.System((128, 128, 1), (3e-9,) * 3, Ms0=1e6, A0=0.0, K1=0.0, Tc=Tc, T=t * Tc, B=(0, 0, 0),
+                          lenmode=0, seed=23)
+    c = S.coeffs()
+    exact, eq1 = length_chain_m2(c, 1, c["sigma"] / 32)
+    assert abs(exact / eq1 - 1) < 1e-5, (exact, eq1)
+    paper, _ = length_chain_m2(c, 0, c["sigma"] / 32)
+    m = S.init_state("uniform")
+    _, cone, win = S.run(m, 300, cone_deg=30, adapt_every=100)
+    xs, sw = [], 300
+    for _ in range(400):
+        _, cone, win = S.run(m, 5, sweep0=sw, cone_deg=cone, adapt_every=100, window=win)
+        sw += 5
+        xs.append((m * m).sum(axis=0).mean())
+    got, se = float(np.mean(xs)), blocked_se(xs, min_blocks=8)
+    print("sampled %.6f +- %.1e, paper-rule law %.6f, Eq. 1 %.6f" % (got, se, paper, eq1))
+    assert abs(paper - eq1) > 6 * se
+    assert abs(got - paper) < 4 * se
 
 
 def test_length_fit_recovers_me_chi(oracle_mod):
