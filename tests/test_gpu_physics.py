@@ -123,3 +123,40 @@ def test_length_move_width(pkg, mf, t):
     print(mf, T, got, sigma)
     assert abs(got / sigma - 1.0) < 1e-5
     ch.close()
+
+
+@pytest.mark.parametrize("lenmove", [0, 1])
+def test_macrospin_length_law(pkg, lenmove):
+    """Isotropic macrospins (3 nm cells, no exchange, anisotropy, field or
+    demag, 0.9 Tc, J = 1/2): the per-sweep FP64 means of |m|^2 over 20,000
+    sweeps of 256x256 cells against the stationary law of the length move's
+    own kernel, solved on a log-length grid from coefficients computed here
+    (me by brentq, chi by Richardson differences, la = V Ms0 / (8 chi me^2 kT),
+    sigma by Eq. 13 with its cap).  The paper's rule (lenmove 0) lands on its
+    law, which differs from the Eq. 1 value; the exact rule (lenmove 1) on the
+    Eq. 1 value."""
+    from paper_2106_05593_amd.hysteresis import blocked_se
+    from test_oracle_sampler import length_chain_m2
+    Tc, T, cell, Ms0 = 700.0, 630.0, 3e-9, 1e6
+    V = cell ** 3
+    me = _solve_m(1, T, Tc, 0.0)
+    dB, lo = 1e-3, 0.5 * me
+    chi = (_solve_m(1, T, Tc, dB, lo=lo) - _solve_m(1, T, Tc, -dB, lo=lo)) / (2 * dB)
+    chi2 = (_solve_m(1, T, Tc, dB / 2, lo=lo) - _solve_m(1, T, Tc, -dB / 2, lo=lo)) / dB
+    chi = chi2 + (chi2 - chi) / 3.0
+    c = {"me": me, "below": 1, "la": V * Ms0 / (8 * chi * me * me * KB * T), "lb": 0.0, "lbc": 0.0,
+         "sigma": min(2.0 * me * np.sqrt(KB * T * chi / (V * Ms0)), 0.03)}
+    law, eq1 = length_chain_m2(c, lenmove, c["sigma"] / 64)
+    ch = pkg.Chain((256, 256, 1), (cell,) * 3, Ms0=Ms0, A0=0.0, K1=0.0, Tc=Tc, T=T, lenmove=lenmove, seed=31,
+                   init=0)
+    assert abs(ch.stats()["sigma"] / c["sigma"] - 1) < 1e-5
+    ch.sweep(500)
+    x = np.concatenate([np.asarray(ch.sweep_record(5000))[:, 3] for _ in range(4)])
+    got, se = float(x.mean()), blocked_se(x)
+    print("lenmove", lenmove, "sampled %.7f +- %.1e, kernel law %.7f, Eq. 1 %.7f" % (got, se, law, eq1), flush=True)
+    ch.close()
+    assert abs(got - law) < 4 * se + 2e-6 * law
+    if lenmove == 0:
+        assert abs(law - eq1) > 20 * se
+    else:
+        assert abs(law / eq1 - 1) < 1e-5
