@@ -218,9 +218,9 @@ mmc_status mmc_get_m(mmc_ctx* ctx, float* out, int on_device);
  * arguments) and replayed, the rest launched directly: the same kernels in
  * the same order, so the same result bits; MMC_SWEEP_GRAPH=0 in the
  * environment keeps direct launches, and so does a call made while the
- * caller captures the context's stream (the sweeps go into that capture).
- * Errors: MMC_ERR_ARG for n < 0, MMC_ERR_STATE after a device
- * error, MMC_ERR_DEVICE from a launch or a failed capture. */
+ * caller captures the context's stream (the sweeps go into that capture) or
+ * on a stream that refuses capture.  Errors: MMC_ERR_ARG for n < 0,
+ * MMC_ERR_STATE after a device error, MMC_ERR_DEVICE from a launch. */
 mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n);
 /* As mmc_sweep, and copies per-sweep statistics to host `series` (n*5 doubles:
  * <mx>, <my>, <mz>, <|m|^2> (FP64 reductions) and the accepted-move count). */

@@ -819,19 +819,34 @@ mmc_status mmc_get_m(mmc_ctx* ctx, float* out, int on_device) {
 // launches.
 static constexpr int kSweepGraph = 16;
 
-static mmc_status sweep_graph_ready(mmc_ctx* ctx) {
-    if (ctx->sg_exec && ctx->sg_version == ctx->version) return MMC_OK;
+// *ready tells whether a current graph exists; a stream that refuses capture
+// or a graph that does not instantiate leaves it false (the caller then
+// launches directly), a failed launch during capture is an error.
+static mmc_status sweep_graph_ready(mmc_ctx* ctx, bool* ready) {
+    *ready = ctx->sg_exec && ctx->sg_version == ctx->version;
+    if (*ready) return MMC_OK;
     if (ctx->sg_exec) { (void)hipGraphExecDestroy(ctx->sg_exec); ctx->sg_exec = nullptr; }
     if (ctx->sg_graph) { (void)hipGraphDestroy(ctx->sg_graph); ctx->sg_graph = nullptr; }
-    HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return MMC_OK;
+    }
     const mmc_status st = enqueue_core(ctx, single(ctx), kSweepGraph, ctx->stream, nullptr, 0, nullptr);
     hipGraph_t gr = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->stream, &gr);
     if (st != MMC_OK) { if (gr) (void)hipGraphDestroy(gr); return st; }
-    HIPCK(e);
+    if (e != hipSuccess || !gr) {
+        (void)hipGetLastError();
+        return MMC_OK;
+    }
     ctx->sg_graph = gr;
-    HIPCK(hipGraphInstantiate(&ctx->sg_exec, ctx->sg_graph, nullptr, nullptr, 0));
+    if (hipGraphInstantiate(&ctx->sg_exec, ctx->sg_graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->sg_exec = nullptr;
+        return MMC_OK;
+    }
     ctx->sg_version = ctx->version;
+    *ready = true;
     return MMC_OK;
 }
 
@@ -844,8 +859,10 @@ mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n) {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIPCK(hipStreamIsCapturing(ctx->stream, &cap));
     if (cap != hipStreamCaptureStatusNone) return enqueue_sweeps(ctx, n, nullptr, 0);   // into the caller's capture
-    s = sweep_graph_ready(ctx);
+    bool ready = false;
+    s = sweep_graph_ready(ctx, &ready);
     if (s != MMC_OK) return s;
+    if (!ready) return enqueue_sweeps(ctx, n, nullptr, 0);
     const int reps = n / kSweepGraph;
     for (int r = 0; r < reps; ++r) HIPCK(hipGraphLaunch(ctx->sg_exec, ctx->stream));
     ctx->host_sweep += (unsigned long long)reps * kSweepGraph;
