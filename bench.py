@@ -151,6 +151,41 @@ def cpu_baseline(seconds_target=15.0):
             "physical_cores": cpu["physical_cores"]}
 
 
+def cpu_batched(n_chains=64, sweeps=1000, seed=0):
+    """The FP64 oracle on the batched workload's chains: for each chain shape,
+    one chain of that shape (its own T and field) timed over 2 sweeps after a
+    warm-up sweep with all host threads (tensor setup not timed), then every
+    chain's `sweeps` sweeps extrapolated linearly from its shape's time per
+    sweep."""
+    from oracle import oracle as O
+    mat = workloads.BASE_MATERIAL
+    params = workloads.batch_chain_params(n_chains, seed)
+    cpu = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cpu["logical_cpus"] or 1))
+    _omp_threads(threads)
+    per_sweep, timed = {}, 0.0
+    for p in params:
+        g = tuple(p["grid"])
+        if g in per_sweep:
+            continue
+        S = O.System(g, (5e-9,) * 3, Ms0=mat["Ms0"], A0=mat["A0"], K1=mat["K1"], Tc=mat["Tc"], T=p["T"], B=p["B"],
+                     demag=True, mf=mat["mf"], chain_id=p["chain_id"], seed=seed)
+        m = S.init_state("uniform")
+        _ = S.plan
+        S.run(m, 1, sweep0=0, cone_deg=30, adapt_every=100)
+        t0 = time.perf_counter()
+        S.run(m, 2, sweep0=1, cone_deg=30, adapt_every=100)
+        dt = time.perf_counter() - t0
+        timed += dt
+        per_sweep[g] = dt / 2
+    total = sum(per_sweep[tuple(p["grid"])] for p in params) * sweeps
+    cells = sum(int(np.prod(p["grid"])) for p in params)
+    return {"chains_per_s": n_chains / total, "cell_updates_per_s": cells * sweeps / total, "threads": threads,
+            "kind": "oracle", "seconds_per_sweep": {"x".join(map(str, g)): round(t, 4) for g, t in per_sweep.items()},
+            "sample": "2 sweeps of one chain per shape (%.1f s with %d threads), every chain's %d sweeps extrapolated "
+                      "linearly" % (timed, threads, sweeps)}
+
+
 def batched_leg(n_chains=64, sweeps=1000, seed=0):
     """Independent chains of uneven size, T and field (64 chains drawn from
     64^2x1, 128^2x1, 256^2x2, 512^2x2 cells of 5 nm, T in [0.2, 1.2] Tc, Hz in
@@ -488,6 +523,9 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        if "batched" in out:
+            print("bench: timing the CPU oracle on the batched chains", file=sys.stderr, flush=True)
+            out["batched"]["cpu_oracle"] = cpu_batched()
     print(json.dumps(out), flush=True)
 
 
