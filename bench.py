@@ -488,6 +488,9 @@ def main():
     ach = per_kernel[dom]["GBs"]
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom), "kernel": dom}
+    if roofline["traffic"]:                     # counted bytes over the same launch time
+        tg = roofline["traffic"] / (per_kernel[dom]["avg_us"] * 1e-6) / 1e9
+        roofline["traffic_GBs"], roofline["traffic_frac"] = round(tg, 1), round(tg / HBM_PEAK_GBS, 4)
     sampled = (args.steps + args.profile_every - 1) // args.profile_every
     roofline["event_sampled_sweeps"] = sampled
     sweep_bytes = sum(algorithmic_bytes(grid, True, n) * int(cnt[k]) for k, n in enumerate(kinds)) / sampled
