@@ -612,3 +612,27 @@ def test_sweep_inside_caller_capture(pkg):
     assert a.get_state()[0] == 2 + 3 * 20 + 17
     a.close()
     b.close()
+
+
+def test_sweep_graphs_of_chains_sharing_a_stream(pkg, monkeypatch):
+    """Two chains created on one caller stream each capture and replay their
+    own sweep graph on it, interleaved; both equal chains advanced by direct
+    launches, bit for bit."""
+    s = torch.cuda.Stream()
+    kw = dict(T=520.0, B=(0.0, 0.0, 0.2), demag=True, seed=9, init=1, adapt_every=8, **MAT)
+    grids = [(64, 40, 2), (96, 33, 1)]
+    a = [pkg.Chain(g, (4e-9, 4e-9, 3e-9), stream=s.cuda_stream, chain_id=i, **kw) for i, g in enumerate(grids)]
+    b = [pkg.Chain(g, (4e-9, 4e-9, 3e-9), chain_id=i, **kw) for i, g in enumerate(grids)]
+    for n in (20, 33, 16):
+        monkeypatch.delenv("MMC_SWEEP_GRAPH", raising=False)
+        for c in a:
+            c.sweep(n)
+        monkeypatch.setenv("MMC_SWEEP_GRAPH", "0")
+        for c in b:
+            c.sweep(n)
+        monkeypatch.delenv("MMC_SWEEP_GRAPH", raising=False)
+    for ca, cb in zip(a, b):
+        assert np.array_equal(ca.get_m(), cb.get_m())
+        assert ca.get_state() == cb.get_state() and ca.stats() == cb.stats()
+        ca.close()
+        cb.close()
