@@ -223,7 +223,10 @@ mmc_status mmc_get_m(mmc_ctx* ctx, float* out, int on_device);
  * MMC_ERR_STATE after a device error, MMC_ERR_DEVICE from a launch. */
 mmc_status mmc_sweep(mmc_ctx* ctx, int32_t n);
 /* As mmc_sweep, and copies per-sweep statistics to host `series` (n*5 doubles:
- * <mx>, <my>, <mz>, <|m|^2> (FP64 reductions) and the accepted-move count). */
+ * <mx>, <my>, <mz>, <|m|^2> (FP64 reductions) and the accepted-move count).
+ * Blocking: synchronises the context's stream first (row i is the sweep that
+ * starts from the device's sweep counter + i, whatever advanced it) and after
+ * the copy.  Not for use while the caller captures the context's stream. */
 mmc_status mmc_sweep_record(mmc_ctx* ctx, int32_t n, double* series);
 
 /* Instrumented sweeps: as mmc_sweep, with HIP events recorded on the
